@@ -1,0 +1,202 @@
+"""Emulated-DGEMM throughput on one MI355X, next to native FP64 DGEMM.
+
+Workload: C = A B with A, B FP64 8192 x 8192, entries U(-1/2, 1/2) *
+exp(phi N(0, 1)) (phi = 0.5), emulated through INT8 residue channels
+(one INT8 MFMA GEMM per modulus, INT32 accumulation). One step is one
+whole emulated call: Scale, Reduce, the residue GEMMs with their fused
+modular epilogue, and Reconstruct. Inputs are resident in HBM before the
+timed region. Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--moduli N] [--scaling W|G|F53]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+INT8_PEAK_TOPS = 5000.0      # MI355X dense INT8 MFMA, TOP/s
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 matrix, TFLOP/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size", type=int, default=8192)
+    ap.add_argument("--phi", type=float, default=0.5)
+    ap.add_argument("--moduli", type=int, default=16)
+    ap.add_argument("--scaling", default="W", choices=["W", "G", "F53"])
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=32,
+                    help="rows of C in the CPU oracle's bounded sample")
+    ap.add_argument("--no-native", action="store_true")
+    return ap.parse_args()
+
+
+def time_stream(fn, iters, warmup):
+    """Mean ms per call of fn() with HIP events on torch's current stream,
+    the stream every library call is launched on."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(iters):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / iters
+
+
+def cpu_baseline(A, B, moduli, mode, rows):
+    """The CPU oracle, as it stands, on a bounded sample: rows [0, rows) of
+    C at full K and N (every step of the scheme, B's scaling and residues
+    over all of B included). Rate in emulated TFLOP/s over the sample."""
+    from oracle import scheme
+    t0 = time.perf_counter()
+    scheme.emulate(A[:rows], B, moduli, mode, blas=True, keep=False)
+    dt = time.perf_counter() - t0
+    n, k = B.shape[1], B.shape[0]
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    return {"value": 2.0 * rows * n * k / dt / 1e12, "unit": "TFLOP/s", "cores": cores,
+            "kind": "oracle",
+            "sample": "rows 0..%d of C at %dx%dx%d (%s, %d moduli): %.1f s on %s; BLAS uses "
+                      "all cores, the rest of the oracle one" % (rows, rows, n, k, mode,
+                                                                 len(moduli), dt,
+                                                                 platform.processor() or
+                                                                 platform.machine())}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2609_37693_amd as oz
+    from workloads import operand_pair
+
+    if not torch.cuda.is_available():
+        print("no HIP device", file=sys.stderr)
+        sys.exit(1)
+    n = args.size
+    A_h, B_h = operand_pair(n, n, n, args.phi, args.seed)
+    A = torch.from_numpy(A_h).cuda()
+    B = torch.from_numpy(B_h).cuda()
+    plan = oz.Plan(num_moduli=args.moduli, scaling=args.scaling)
+    moduli = plan.moduli()
+    C = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    ws = torch.empty(plan.workspace_size(n, n, n), dtype=torch.uint8, device="cuda")
+
+    def step():
+        oz.dgemm(A, B, plan, out=C, workspace=ws)
+
+    # whole-call throughput: W warmup calls, then exactly K timed calls
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1) / args.steps
+    flops = 2.0 * n * n * n
+    value = flops / (ms * 1e-3) / 1e12
+
+    # dominant kernel: the residue GEMMs, one launch over all moduli
+    sa, sb = oz.scale(A, B, plan)
+    pa, pb = oz.reduce(A, B, sa, sb, plan)
+    z = torch.empty((len(moduli),) + tuple(plan.plane_dims(n, n, n)[:2]), dtype=torch.uint8,
+                    device="cuda")
+    lib = oz._lib.load()
+    import ctypes as C_
+
+    def gemm_only():
+        oz._lib.check(lib.ozemu_residue_gemm(plan.handle, oz._stream_ptr(), n, n, n,
+                                             C_.c_void_p(pa.data_ptr()),
+                                             C_.c_void_p(pb.data_ptr()),
+                                             C_.c_void_p(z.data_ptr())))
+    gemm_ms = time_stream(gemm_only, max(5, args.steps // 2), 2)
+    ops = 2.0 * len(moduli) * n * n * n
+    achieved = ops / (gemm_ms * 1e-3) / 1e12
+
+    # per-phase times (synchronized separately, as in a profile)
+    phases = {
+        "scale": time_stream(lambda: oz.scale(A, B, plan), 5, 1),
+        "reduce": time_stream(lambda: oz.reduce(A, B, sa, sb, plan), 5, 1),
+        "residue_gemm": gemm_ms,
+        "reconstruct": time_stream(lambda: oz.reconstruct(z, sa, sb, n, n, n, plan, out=C), 5, 1),
+    }
+
+    # accuracy against native FP64 on the same GPU
+    step()
+    torch.cuda.synchronize()
+    native_ms = None
+    ref = A @ B
+    if not args.no_native:
+        native_ms = time_stream(lambda: torch.matmul(A, B, out=ref), max(5, args.steps // 2), 2)
+    rel_fro = float(torch.linalg.norm(C - ref) / torch.linalg.norm(ref))
+    absAB = A.abs() @ B.abs()
+    scaled_vs_native = float(torch.max((C - ref).abs() / absAB))
+
+    out = {
+        "metric": "emulated DGEMM TFLOP/s vs native FP64 MFMA at 8192^3, at <=2^-50 scaled error",
+        "value": value,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": "emulated DGEMM m=n=k=%d, FP64 entries U(-1/2,1/2)*exp(%g*N(0,1)), "
+                               "INT8 residue path" % (n, args.phi),
+                   "m": n, "n": n, "k": n, "phi": args.phi, "moduli": len(moduli),
+                   "scaling_mode": args.scaling, "seed": args.seed},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS,
+                     "unit": "TFLOP/s", "frac": achieved / INT8_PEAK_TOPS, "traffic": None,
+                     "kernel": "residue_gemm_kernel (INT8 MFMA, all moduli, one launch)",
+                     "kernel_ms": gemm_ms},
+        "phases_ms": phases,
+        "native_fp64": {"ms": native_ms,
+                        "value": (flops / (native_ms * 1e-3) / 1e12) if native_ms else None,
+                        "frac_of_peak": (flops / (native_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS)
+                        if native_ms else None},
+        "speedup_vs_native": (native_ms / ms) if native_ms else None,
+        "rel_frobenius_vs_native": rel_fro,
+        "max_scaled_diff_vs_native": scaled_vs_native,
+        "wall_s_timed": wall,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(A_h, B_h, moduli, args.scaling, args.cpu_rows)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,160 @@
+/*
+ * ozemu.h - FP64 matrix multiplication emulated on low-precision matrix
+ * units of AMD Instinct MI355X (gfx950), residue-number-system style.
+ *
+ * Method (Mazumder, Calotoiu, Hoefler, "FP64 Is All You Want, INT8 Is All
+ * You Need, FP4/6/8 Is All You Have"): rows of A and columns of B are scaled
+ * by powers of two and truncated to integers A', B' (Sec. II-A, eq.
+ * "convert"); A' and B' are reduced modulo pairwise-coprime moduli (Sec.
+ * II-B); each modulus's product runs as an exact INT8 GEMM with INT32
+ * accumulation (Sec. IV-C); the epilogue reduces each product modulo its
+ * modulus (Sec. V-C); Reconstruct applies the CRT, rounds once and unscales
+ * (Sec. V-A, V-C). The result is C = RN(A'B' * 2^-(s_i + t_j)) entry by
+ * entry, one rounding, whenever the CRT window (eq. "ov-crtgen") and the
+ * accumulator bound (eq. "ov-accgen") hold; the library checks both before
+ * any launch.
+ *
+ * Conventions for every entry point:
+ *  - Matrices are row-major FP64 with a leading dimension (elements between
+ *    consecutive rows): A is m x k (lda >= k), B is k x n (ldb >= n), C is
+ *    m x n (ldc >= n). Leading dimensions are ignored for empty operands.
+ *  - Pointers named A, B, C, workspace, shifts, planes and residues are
+ *    device pointers owned by the caller; the library never allocates device
+ *    memory and never frees caller memory. Host arrays are marked "host".
+ *  - `stream` is a hipStream_t passed as void* (NULL: the null stream). All
+ *    launches are asynchronous on it; no entry point synchronizes.
+ *  - Every entry point returns an ozemu_status; arguments are validated on
+ *    the host before any launch, and on an error nothing is launched.
+ *    ozemu_last_error() gives a message for the calling thread's last error.
+ *  - m = 0 or n = 0 is a no-op; k = 0 writes zeros to C.
+ */
+#ifndef OZEMU_H
+#define OZEMU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OZEMU_OK = 0,
+    OZEMU_ERR_INVALID_ARG = -1,  /* bad pointer, size, leading dimension, mode */
+    OZEMU_ERR_K_TOO_LARGE = -2,  /* k above the exactness caps of the plan     */
+    OZEMU_ERR_UNSUPPORTED = -3,  /* format or option not built                  */
+    OZEMU_ERR_WORKSPACE = -4,    /* workspace NULL or smaller than required     */
+    OZEMU_ERR_HIP = -5           /* a HIP launch or runtime call failed         */
+} ozemu_status;
+
+/* Low-precision format of the residue GEMMs (Sec. III-A alphabets). */
+typedef enum {
+    OZEMU_INT8 = 0  /* one INT8 GEMM per modulus, moduli <= 256 (Sec. IV-C) */
+} ozemu_format;
+
+/* How many bits of each row of A / column of B are kept (Sec. II-A).
+ *  F53:    53 bits, the paper's scaling (mu, nu of eq. "convert"); refused
+ *          when 2 k (2^53 - 1)^2 >= P (eq. "ov-crt").
+ *  WINDOW: the moduli count is the accuracy knob: with
+ *          w = floor(log2((P - 1) / (2 k))), A keeps ceil(w / 2) bits and B
+ *          floor(w / 2), so the CRT window holds for any data.
+ *  BOUND:  bound-adaptive: one extra INT8 GEMM of 6-bit magnitude bounds
+ *          |A| |B| entrywise and sets per-row / per-column bits so that
+ *          sum_h |A'_ih| |B'_hj| <= (P - 1) / 2 for every entry. */
+typedef enum {
+    OZEMU_SCALE_F53 = 0,
+    OZEMU_SCALE_WINDOW = 1,
+    OZEMU_SCALE_BOUND = 2
+} ozemu_scaling;
+
+/* Row or column shift written for a row of A / column of B holding a NaN or
+ * an infinity; every entry of C it touches is NaN. */
+#define OZEMU_SHIFT_NONFINITE INT32_MIN
+
+typedef struct ozemu_plan_s* ozemu_plan;
+
+/* Create a plan: the `num_moduli` pairwise-coprime moduli in [2, 256] of
+ * largest product (Sec. III-A configuration; 2 <= num_moduli <= 32), the
+ * scaling mode, CRT constants and caps. Host memory only; the plan owns it
+ * and ozemu_plan_destroy frees it. *out is set to NULL on failure. */
+ozemu_status ozemu_plan_create(ozemu_plan* out, int format, int num_moduli, int scaling);
+
+/* Same with an explicit modulus list (host array of `count` ints, pairwise
+ * coprime, each in [2, 256]; any order; stored sorted descending). */
+ozemu_status ozemu_plan_create_moduli(ozemu_plan* out, int format, int count,
+                                      const int32_t* moduli, int scaling);
+
+ozemu_status ozemu_plan_destroy(ozemu_plan plan);
+
+/* Moduli of the plan, descending, into host array `out` of capacity `cap`;
+ * *count receives the number of moduli. */
+ozemu_status ozemu_plan_moduli(ozemu_plan plan, int32_t* out, int cap, int* count);
+
+/* Kept bits (beta_A, beta_B) the plan uses at inner dimension k in modes F53
+ * and WINDOW (BOUND decides them per row and column on the device). */
+ozemu_status ozemu_plan_kept_bits(ozemu_plan plan, int64_t k, int* beta_a, int* beta_b);
+
+/* Largest k the plan accepts: min(kappa_rec, kappa_acc) of eq. "caps"
+ * (kappa_rec only limits F53; WINDOW and BOUND adapt their bits to k). */
+ozemu_status ozemu_plan_k_max(ozemu_plan plan, int64_t* k_max);
+
+/* Padded sizes of the residue planes: planes of A are [N][m_pad][k_pad],
+ * planes of B [N][n_pad][k_pad] (K-contiguous), residues [N][m_pad][n_pad],
+ * all int8 / uint8 with these exact strides. */
+ozemu_status ozemu_plane_dims(ozemu_plan plan, int64_t m, int64_t n, int64_t k,
+                              int64_t* m_pad, int64_t* n_pad, int64_t* k_pad);
+
+/* Bytes of device workspace ozemu_dgemm needs for this shape. */
+ozemu_status ozemu_workspace_size(ozemu_plan plan, int64_t m, int64_t n, int64_t k,
+                                  size_t* bytes);
+
+/* C = A B, emulated (Sec. V-A: Scale, Reduce, GEMMs, Epilogue, Reconstruct).
+ * `workspace` must hold ozemu_workspace_size bytes, 256-byte aligned. */
+ozemu_status ozemu_dgemm(ozemu_plan plan, void* stream, int64_t m, int64_t n, int64_t k,
+                         const double* A, int64_t lda, const double* B, int64_t ldb,
+                         double* C, int64_t ldc, void* workspace, size_t ws_bytes);
+
+/* ---- The five phases as separate calls (Sec. V-A), for callers that keep
+ * intermediates (autograd, verification). Shapes and strides as in
+ * ozemu_plane_dims. ---- */
+
+/* Scale (Sec. V-A phase 1): shift_a[i] = s_i (A' = trunc(A * 2^s_i) per row),
+ * shift_b[j] = t_j per column; 0 for a zero row/column,
+ * OZEMU_SHIFT_NONFINITE for one with a NaN or infinity. Mode BOUND runs its
+ * bound GEMM here and needs `workspace` (ozemu_workspace_size bytes); the
+ * other modes accept NULL. */
+ozemu_status ozemu_scale(ozemu_plan plan, void* stream, int64_t m, int64_t n, int64_t k,
+                         const double* A, int64_t lda, const double* B, int64_t ldb,
+                         int32_t* shift_a, int32_t* shift_b, void* workspace, size_t ws_bytes);
+
+/* Reduce (phase 2): planes_a[l][i][h] = balanced residue of A'_ih modulo
+ * m_l in [-floor(m/2), ceil(m/2) - 1] as int8 (two's complement);
+ * planes_b[l][j][h] likewise for B'_hj (transposed, K-contiguous). Padding
+ * rows and columns are written as 0. */
+ozemu_status ozemu_reduce(ozemu_plan plan, void* stream, int64_t m, int64_t n, int64_t k,
+                          const double* A, int64_t lda, const double* B, int64_t ldb,
+                          const int32_t* shift_a, const int32_t* shift_b,
+                          int8_t* planes_a, int8_t* planes_b);
+
+/* GEMMs and epilogue (phases 3-4): residues[l][i][j] = (sum_h
+ * planes_a[l][i][h] planes_b[l][j][h]) mod m_l in [0, m_l), INT32 sums. */
+ozemu_status ozemu_residue_gemm(ozemu_plan plan, void* stream, int64_t m, int64_t n, int64_t k,
+                                const int8_t* planes_a, const int8_t* planes_b,
+                                uint8_t* residues);
+
+/* Reconstruct (phase 5): C_ij = RN(X_ij * 2^-(s_i + t_j)), X_ij the
+ * balanced CRT solution of residues[.][i][j], one rounding (ties to even,
+ * subnormals and overflow included). */
+ozemu_status ozemu_reconstruct(ozemu_plan plan, void* stream, int64_t m, int64_t n, int64_t k,
+                               const uint8_t* residues, const int32_t* shift_a,
+                               const int32_t* shift_b, double* C, int64_t ldc);
+
+const char* ozemu_status_string(int status);
+const char* ozemu_last_error(void);
+const char* ozemu_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OZEMU_H */

@@ -33,7 +33,8 @@ Steps (Sec. II-A eq. "convert", Sec. II-B, Sec. III-C, Sec. V-A)
 
 Non-finite input (the paper is silent): every entry of C in a row of A or
 column of B holding a NaN or an infinity is NaN; those rows and columns
-are otherwise treated as zero.
+are otherwise treated as zero rows and columns (shift 0, zero residues, and
+no contribution to the bound product of reading "G").
 """
 from __future__ import annotations
 
@@ -90,19 +91,24 @@ def truncate(X: np.ndarray, s: np.ndarray, axis: int):
     2**beta <= 2**127, far from overflow, and a result that underflows is
     below 1 and truncates to 0 either way), and ``numpy.trunc`` rounds
     toward zero. The integers are returned as an object array of Python
-    ints (exact for any beta).
+    ints (exact for any beta), or as int64 when every value is below 2**62.
     """
     X = np.where(np.isfinite(X), X, 0.0)
     sh = s[:, None] if axis == 1 else s[None, :]
     T = np.trunc(np.ldexp(X, sh))
+    if T.size == 0 or np.max(np.abs(T)) < 2.0 ** 62:
+        return T.astype(np.int64)  # every value is an integer below 2**62
     return exact.to_object_ints(T)
 
 
 def balanced_residues(Xint: np.ndarray, m: int) -> np.ndarray:
     """Residues of integer matrix Xint modulo m in [-floor(m/2), ceil(m/2)-1],
     as int64. Python's % returns values in [0, m) for m > 0."""
-    r = np.vectorize(lambda v: int(v) % m, otypes=[np.int64])(Xint) \
-        if Xint.size else np.zeros(Xint.shape, dtype=np.int64)
+    if Xint.dtype == np.int64:
+        r = np.mod(Xint, m)
+    else:
+        r = np.vectorize(lambda v: int(v) % m, otypes=[np.int64])(Xint) \
+            if Xint.size else np.zeros(Xint.shape, dtype=np.int64)
     half = (m + 1) // 2
     return np.where(r >= half, r - m, r).astype(np.int64)
 
@@ -154,10 +160,15 @@ def round_scaled(X: np.ndarray, s: np.ndarray, t: np.ndarray) -> np.ndarray:
 def bound_planes(X: np.ndarray, e: np.ndarray, axis: int) -> np.ndarray:
     """Reading "G", first step: abar = ceil(|x| * 2**(6 - e)) per row
     (axis=1) or column (axis=0), an integer in [0, 64] because
-    |x| < 2**e. Non-finite entries count as zero."""
+    |x| < 2**e. Non-finite entries count as zero. ``numpy.ldexp`` is exact
+    unless its result underflows to 0, which only happens for a nonzero x
+    whose exact scaled value lies in (0, 1): its ceiling is 1."""
     X = np.where(np.isfinite(X), X, 0.0)
     sh = (6 - e)[:, None] if axis == 1 else (6 - e)[None, :]
-    return np.ceil(np.ldexp(np.abs(X), sh)).astype(np.int64)
+    V = np.ldexp(np.abs(X), sh)
+    out = np.ceil(V).astype(np.int64)
+    out[(V == 0) & (X != 0)] = 1
+    return out
 
 
 def bound_shifts(A, B, P: int):
@@ -196,11 +207,22 @@ def bound_shifts(A, B, P: int):
     return side(gmax_r), side(gmax_c), abar, bbar, G
 
 
+def _finite_parts(A, B):
+    """(A0, B0, finA, finB): rows of A and columns of B holding a NaN or an
+    infinity replaced by zeros (the reading for non-finite input)."""
+    finA = np.all(np.isfinite(A), axis=1)
+    finB = np.all(np.isfinite(B), axis=0)
+    A0 = np.where(finA[:, None], A, 0.0)
+    B0 = np.where(finB[None, :], B, 0.0)
+    return A0, B0, finA, finB
+
+
 def _shifts(A, B, moduli, mode):
     K = A.shape[1]
     P = product(moduli)
-    eA, nzA, finA = frexp_exponents(A, 1)
-    eB, nzB, finB = frexp_exponents(B, 0)
+    A, B, finA, finB = _finite_parts(A, B)
+    eA, nzA, _ = frexp_exponents(A, 1)
+    eB, nzB, _ = frexp_exponents(B, 0)
     if mode == "G":
         sig, tau, _, _, _ = bound_shifts(A, B, P)
         s = shifts_from_bits(eA, nzA, sig)
@@ -229,6 +251,7 @@ def emulate(A: np.ndarray, B: np.ndarray, moduli, mode: str = "W",
     M, K = A.shape
     N = B.shape[1]
     s, t, finA, finB, bits = _shifts(A, B, moduli, mode)
+    A, B, _, _ = _finite_parts(A, B)
     Ai = truncate(A, s, 1)
     Bi = truncate(B, t, 0)
     RA, RB, Z = [], [], np.zeros((len(moduli), M, N), dtype=np.int64)
@@ -253,6 +276,7 @@ def definition_product(A: np.ndarray, B: np.ndarray, moduli, mode: str = "W"):
     A = np.asarray(A, dtype=np.float64)
     B = np.asarray(B, dtype=np.float64)
     s, t, finA, finB, _ = _shifts(A, B, moduli, mode)
+    A, B, _, _ = _finite_parts(A, B)
     X = exact.exact_int_matmul(truncate(A, s, 1), truncate(B, t, 0))
     C = round_scaled(X, s, t)
     bad = (~finA)[:, None] | (~finB)[None, :]

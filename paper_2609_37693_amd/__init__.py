@@ -1,0 +1,206 @@
+"""FP64 GEMM emulated on the INT8 matrix cores of MI355X (gfx950).
+
+Python binding of libozemu (C-ABI in ``include/ozemu.h``). Every step of
+the computation runs in the library's HIP kernels; this module only
+marshals torch tensors (device memory), the current HIP stream and sizes.
+
+    import torch, paper_2609_37693_amd as oz
+    plan = oz.Plan(num_moduli=16, scaling="W")
+    C = oz.dgemm(A, B, plan)          # A, B: float64 CUDA tensors
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+from . import _lib
+from ._lib import OzemuError, SCALING, SHIFT_NONFINITE
+
+__all__ = ["Plan", "dgemm", "scale", "reduce", "residue_gemm", "reconstruct", "OzemuError",
+           "SHIFT_NONFINITE", "version"]
+
+
+def version() -> str:
+    return _lib.load().ozemu_version().decode()
+
+
+class Plan:
+    """An emulation plan: modulus set, scaling mode, CRT constants (host)."""
+
+    def __init__(self, num_moduli: int = 16, scaling: str = "W", moduli=None):
+        lib = _lib.load()
+        self._h = C.c_void_p()
+        self.scaling = scaling
+        mode = SCALING[scaling]
+        if moduli is not None:
+            arr = (C.c_int32 * len(moduli))(*[int(m) for m in moduli])
+            _lib.check(lib.ozemu_plan_create_moduli(C.byref(self._h), _lib.OZEMU_INT8,
+                                                    len(moduli), arr, mode))
+        else:
+            _lib.check(lib.ozemu_plan_create(C.byref(self._h), _lib.OZEMU_INT8,
+                                             int(num_moduli), mode))
+        self._lib = lib
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.ozemu_plan_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def moduli(self):
+        cnt = C.c_int()
+        _lib.check(self._lib.ozemu_plan_moduli(self._h, None, 0, C.byref(cnt)))
+        out = (C.c_int32 * cnt.value)()
+        _lib.check(self._lib.ozemu_plan_moduli(self._h, out, cnt.value, C.byref(cnt)))
+        return list(out)
+
+    def kept_bits(self, k: int):
+        a, b = C.c_int(), C.c_int()
+        _lib.check(self._lib.ozemu_plan_kept_bits(self._h, int(k), C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def k_max(self) -> int:
+        v = C.c_int64()
+        _lib.check(self._lib.ozemu_plan_k_max(self._h, C.byref(v)))
+        return v.value
+
+    def plane_dims(self, m: int, n: int, k: int):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        _lib.check(self._lib.ozemu_plane_dims(self._h, int(m), int(n), int(k), C.byref(a),
+                                              C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def workspace_size(self, m: int, n: int, k: int) -> int:
+        v = C.c_size_t()
+        _lib.check(self._lib.ozemu_workspace_size(self._h, int(m), int(n), int(k), C.byref(v)))
+        return v.value
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else C.c_void_p()
+
+
+def _matrix(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.dim() != 2:
+        raise TypeError("%s must be a 2-D float64 tensor" % name)
+    if not t.is_cuda:
+        raise TypeError("%s must be on a HIP device" % name)
+    if t.stride(1) != 1 and t.numel() > 0:
+        t = t.contiguous()
+    return t, (t.stride(0) if t.numel() > 0 else max(1, t.shape[1]))
+
+
+class _Workspace:
+    """Grow-only device workspace per (device, plan) for dgemm calls."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes, device):
+        torch = _torch()
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+            if self.buf.data_ptr() % 256:
+                raise RuntimeError("workspace allocation is not 256-byte aligned")
+        return self.buf
+
+
+_WS = {}
+
+
+def dgemm(A, B, plan: Plan, out=None, workspace=None):
+    """C = A @ B emulated through the plan's INT8 residue channels."""
+    torch = _torch()
+    A, lda = _matrix(A, "A")
+    B, ldb = _matrix(B, "B")
+    m, k = A.shape
+    k2, n = B.shape
+    if k != k2:
+        raise ValueError("inner dimensions differ: %d vs %d" % (k, k2))
+    if out is None:
+        out = torch.empty((m, n), dtype=torch.float64, device=A.device)
+    ldc = out.stride(0) if out.numel() > 0 else max(1, n)
+    nbytes = plan.workspace_size(m, n, k)
+    if workspace is None:
+        workspace = _WS.setdefault((A.device, id(plan)), _Workspace()).get(nbytes, A.device)
+    _lib.check(plan._lib.ozemu_dgemm(plan.handle, _stream_ptr(), m, n, k, _ptr(A), lda, _ptr(B),
+                                     ldb, _ptr(out), ldc, _ptr(workspace),
+                                     workspace.numel() if workspace is not None else 0))
+    return out
+
+
+def scale(A, B, plan: Plan, workspace=None):
+    """(shift_a, shift_b) int32 tensors of the Scale phase."""
+    torch = _torch()
+    A, lda = _matrix(A, "A")
+    B, ldb = _matrix(B, "B")
+    m, k = A.shape
+    n = B.shape[1]
+    sa = torch.empty(max(m, 1), dtype=torch.int32, device=A.device)
+    sb = torch.empty(max(n, 1), dtype=torch.int32, device=A.device)
+    if workspace is None and plan.scaling == "G":
+        workspace = torch.empty(plan.workspace_size(m, n, k), dtype=torch.uint8, device=A.device)
+    _lib.check(plan._lib.ozemu_scale(plan.handle, _stream_ptr(), m, n, k, _ptr(A), lda, _ptr(B),
+                                     ldb, _ptr(sa), _ptr(sb), _ptr(workspace),
+                                     workspace.numel() if workspace is not None else 0))
+    return sa[:m], sb[:n]
+
+
+def reduce(A, B, shift_a, shift_b, plan: Plan):
+    """(planes_a [N, m_pad, k_pad], planes_b [N, n_pad, k_pad]) int8 tensors."""
+    torch = _torch()
+    A, lda = _matrix(A, "A")
+    B, ldb = _matrix(B, "B")
+    m, k = A.shape
+    n = B.shape[1]
+    mp, np_, kp = plan.plane_dims(m, n, k)
+    N = len(plan.moduli())
+    pa = torch.empty((N, mp, kp), dtype=torch.int8, device=A.device)
+    pb = torch.empty((N, np_, kp), dtype=torch.int8, device=A.device)
+    _lib.check(plan._lib.ozemu_reduce(plan.handle, _stream_ptr(), m, n, k, _ptr(A), lda, _ptr(B),
+                                      ldb, _ptr(shift_a), _ptr(shift_b), _ptr(pa), _ptr(pb)))
+    return pa, pb
+
+
+def residue_gemm(planes_a, planes_b, m: int, n: int, k: int, plan: Plan):
+    """residues [N, m_pad, n_pad] uint8: (planes_a planes_b^T) mod m_l."""
+    torch = _torch()
+    mp, np_, kp = plan.plane_dims(m, n, k)
+    N = len(plan.moduli())
+    if tuple(planes_a.shape) != (N, mp, kp) or tuple(planes_b.shape) != (N, np_, kp):
+        raise ValueError("plane shapes do not match the plan's padded dimensions")
+    z = torch.empty((N, mp, np_), dtype=torch.uint8, device=planes_a.device)
+    _lib.check(plan._lib.ozemu_residue_gemm(plan.handle, _stream_ptr(), m, n, k,
+                                            _ptr(planes_a.contiguous()),
+                                            _ptr(planes_b.contiguous()), _ptr(z)))
+    return z
+
+
+def reconstruct(residues, shift_a, shift_b, m: int, n: int, k: int, plan: Plan, out=None):
+    """C (m x n float64) from residues and shifts."""
+    torch = _torch()
+    mp, np_, kp = plan.plane_dims(m, n, k)
+    N = len(plan.moduli())
+    if tuple(residues.shape) != (N, mp, np_):
+        raise ValueError("residue shape does not match the plan's padded dimensions")
+    if out is None:
+        out = torch.empty((m, n), dtype=torch.float64, device=residues.device)
+    ldc = out.stride(0) if out.numel() > 0 else max(1, n)
+    _lib.check(plan._lib.ozemu_reconstruct(plan.handle, _stream_ptr(), m, n, k,
+                                           _ptr(residues.contiguous()), _ptr(shift_a),
+                                           _ptr(shift_b), _ptr(out), ldc))
+    return out

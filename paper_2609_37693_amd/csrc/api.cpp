@@ -1,0 +1,421 @@
+// C-ABI of libozemu: argument validation, workspace layout and the call
+// pipeline of Sec. V-A (Scale, Reduce, GEMMs with fused epilogue,
+// Reconstruct) on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ozemu.h"
+#include "ozemu_internal.hpp"
+#include "plan.hpp"
+
+struct ozemu_plan_s {
+    ozemu::Plan p;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ozemu_status fail(ozemu_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+ozemu_status ok() { return OZEMU_OK; }
+
+ozemu_status hip_check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return OZEMU_OK;
+    return fail(OZEMU_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int64_t round_up(int64_t v, int64_t t) { return (v + t - 1) / t * t; }
+
+struct Dims {
+    int64_t m_pad, n_pad, k_pad;
+};
+
+Dims dims_of(int64_t m, int64_t n, int64_t k) {
+    return {round_up(m, ozemu::kTileM), round_up(n, ozemu::kTileN), round_up(k, ozemu::kTileK)};
+}
+
+struct Layout {
+    size_t key_a, key_b, shift_a, shift_b, planes_a, planes_b, residues, bar_a, bar_b, gmax_a,
+        gmax_b, total;
+};
+
+Layout layout_of(const ozemu::Plan& p, int64_t m, int64_t n, int64_t k) {
+    Dims d = dims_of(m, n, k);
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    const size_t N = (size_t)p.n;
+    L.key_a = take(sizeof(int32_t) * (size_t)d.m_pad);
+    L.key_b = take(sizeof(int32_t) * (size_t)d.n_pad);
+    L.shift_a = take(sizeof(int32_t) * (size_t)d.m_pad);
+    L.shift_b = take(sizeof(int32_t) * (size_t)d.n_pad);
+    L.planes_a = take(N * (size_t)d.m_pad * (size_t)d.k_pad);
+    L.planes_b = take(N * (size_t)d.n_pad * (size_t)d.k_pad);
+    L.residues = take(N * (size_t)d.m_pad * (size_t)d.n_pad);
+    if (p.scaling == OZEMU_SCALE_BOUND) {
+        L.bar_a = take((size_t)d.m_pad * (size_t)d.k_pad);
+        L.bar_b = take((size_t)d.n_pad * (size_t)d.k_pad);
+        L.gmax_a = take(sizeof(int32_t) * (size_t)d.m_pad);
+        L.gmax_b = take(sizeof(int32_t) * (size_t)d.n_pad);
+    }
+    L.total = off;
+    return L;
+}
+
+// Scale-phase workspace needs: only the bound-adaptive mode uses it.
+size_t scale_ws_need(const ozemu::Plan& p, int64_t m, int64_t n, int64_t k) {
+    return p.scaling == OZEMU_SCALE_BOUND ? layout_of(p, m, n, k).total : 0;
+}
+
+ozemu_status check_plan(ozemu_plan plan) {
+    if (!plan) return fail(OZEMU_ERR_INVALID_ARG, "plan is NULL");
+    return ok();
+}
+
+ozemu_status check_shape(const ozemu::Plan& p, int64_t m, int64_t n, int64_t k) {
+    if (m < 0 || n < 0 || k < 0) return fail(OZEMU_ERR_INVALID_ARG, "negative dimension");
+    if (m > (1ll << 31) || n > (1ll << 31)) return fail(OZEMU_ERR_INVALID_ARG, "dimension too large");
+    if (k > p.kappa_acc)
+        return fail(OZEMU_ERR_K_TOO_LARGE,
+                    "k = " + std::to_string(k) + " exceeds the INT32 accumulation cap " +
+                        std::to_string(p.kappa_acc) + " of this modulus set");
+    if (p.scaling == OZEMU_SCALE_F53 && k > 0 && !ozemu::window_holds(p, k, 53, 53))
+        return fail(OZEMU_ERR_K_TOO_LARGE,
+                    "k = " + std::to_string(k) +
+                        " exceeds the reconstruction cap of this modulus set at 53 bits");
+    if (p.scaling == OZEMU_SCALE_WINDOW && k > 0 && ozemu::window_bits(p, k) < 2)
+        return fail(OZEMU_ERR_K_TOO_LARGE, "modulus product too small for this k");
+    if (p.scaling == OZEMU_SCALE_BOUND && k > 524287)
+        return fail(OZEMU_ERR_K_TOO_LARGE, "bound product would overflow INT32");
+    return ok();
+}
+
+ozemu_status check_operands(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda,
+                            const void* B, int64_t ldb) {
+    if (m > 0 && k > 0) {
+        if (!A) return fail(OZEMU_ERR_INVALID_ARG, "A is NULL");
+        if (lda < k) return fail(OZEMU_ERR_INVALID_ARG, "lda < k");
+    }
+    if (k > 0 && n > 0) {
+        if (!B) return fail(OZEMU_ERR_INVALID_ARG, "B is NULL");
+        if (ldb < n) return fail(OZEMU_ERR_INVALID_ARG, "ldb < n");
+    }
+    return ok();
+}
+
+void kept_bits_of(const ozemu::Plan& p, int64_t k, int& ba, int& bb) {
+    if (p.scaling == OZEMU_SCALE_F53) {
+        ba = bb = 53;
+        return;
+    }
+    int w = ozemu::window_bits(p, k);
+    ba = (w + 1) / 2;
+    bb = w / 2;
+    if (ba > ozemu::kBetaCap) ba = ozemu::kBetaCap;
+    if (bb > ozemu::kBetaCap) bb = ozemu::kBetaCap;
+}
+
+// Scale with all arguments validated; ws may be NULL unless BOUND.
+ozemu_status run_scale(const ozemu::Plan& p, hipStream_t st, int64_t m, int64_t n, int64_t k,
+                       const double* A, int64_t lda, const double* B, int64_t ldb, int32_t* sa,
+                       int32_t* sb, char* ws) {
+    using namespace ozemu;
+    if (p.scaling != OZEMU_SCALE_BOUND) {
+        int ba, bb;
+        kept_bits_of(p, k, ba, bb);
+        if (k == 0) {
+            ozemu_status s = hip_check(launch_fill_i32(st, m, 0, sa), "fill");
+            if (s) return s;
+            return hip_check(launch_fill_i32(st, n, 0, sb), "fill");
+        }
+        ozemu_status s = hip_check(launch_scale_rows(st, m, k, A, lda, sa), "scale_rows");
+        if (s) return s;
+        s = hip_check(launch_scale_cols(st, k, n, B, ldb, sb), "scale_cols");
+        if (s) return s;
+        s = hip_check(launch_keys_to_shifts(st, m, sa, ba, nullptr), "shifts_a");
+        if (s) return s;
+        return hip_check(launch_keys_to_shifts(st, n, sb, bb, nullptr), "shifts_b");
+    }
+    Layout L = layout_of(p, m, n, k);
+    Dims d = dims_of(m, n, k);
+    int32_t* key_a = reinterpret_cast<int32_t*>(ws + L.key_a);
+    int32_t* key_b = reinterpret_cast<int32_t*>(ws + L.key_b);
+    int8_t* bar_a = reinterpret_cast<int8_t*>(ws + L.bar_a);
+    int8_t* bar_b = reinterpret_cast<int8_t*>(ws + L.bar_b);
+    int32_t* gmax_a = reinterpret_cast<int32_t*>(ws + L.gmax_a);
+    int32_t* gmax_b = reinterpret_cast<int32_t*>(ws + L.gmax_b);
+    if (k == 0) {
+        ozemu_status s = hip_check(launch_fill_i32(st, m, 0, sa), "fill");
+        if (s) return s;
+        return hip_check(launch_fill_i32(st, n, 0, sb), "fill");
+    }
+    ozemu_status s = hip_check(launch_scale_rows(st, m, k, A, lda, key_a), "scale_rows");
+    if (!s) s = hip_check(launch_scale_cols(st, k, n, B, ldb, key_b), "scale_cols");
+    if (!s)
+        s = hip_check(launch_bound_planes_a(st, m, k, A, lda, key_a, d.m_pad, d.k_pad, bar_a),
+                      "bound_planes_a");
+    if (!s)
+        s = hip_check(launch_bound_planes_b(st, k, n, B, ldb, key_b, d.n_pad, d.k_pad, bar_b),
+                      "bound_planes_b");
+    if (!s)
+        s = hip_check(launch_bound_gemm(st, d.m_pad, d.n_pad, d.k_pad, bar_a, bar_b, gmax_a, gmax_b),
+                      "bound_gemm");
+    const int L2 = half_window_bits(p);
+    if (!s) s = hip_check(launch_bound_shifts(st, m, key_a, gmax_a, L2, sa), "bound_shifts_a");
+    if (!s) s = hip_check(launch_bound_shifts(st, n, key_b, gmax_b, L2, sb), "bound_shifts_b");
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ozemu_version(void) { return "ozemu 0.1 (gfx950)"; }
+
+const char* ozemu_last_error(void) { return g_last_error.c_str(); }
+
+const char* ozemu_status_string(int status) {
+    switch (status) {
+        case OZEMU_OK: return "OZEMU_OK";
+        case OZEMU_ERR_INVALID_ARG: return "OZEMU_ERR_INVALID_ARG";
+        case OZEMU_ERR_K_TOO_LARGE: return "OZEMU_ERR_K_TOO_LARGE";
+        case OZEMU_ERR_UNSUPPORTED: return "OZEMU_ERR_UNSUPPORTED";
+        case OZEMU_ERR_WORKSPACE: return "OZEMU_ERR_WORKSPACE";
+        case OZEMU_ERR_HIP: return "OZEMU_ERR_HIP";
+        default: return "unknown status";
+    }
+}
+
+ozemu_status ozemu_plan_create_moduli(ozemu_plan* out, int format, int count,
+                                      const int32_t* moduli, int scaling) {
+    if (!out) return fail(OZEMU_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (format != OZEMU_INT8) return fail(OZEMU_ERR_UNSUPPORTED, "only OZEMU_INT8 is built");
+    if (count < 2 || count > ozemu::kMaxModuli || !moduli)
+        return fail(OZEMU_ERR_INVALID_ARG, "number of moduli must be in [2, 32]");
+    std::vector<int> ms(moduli, moduli + count);
+    ozemu_plan p = new (std::nothrow) ozemu_plan_s;
+    if (!p) return fail(OZEMU_ERR_INVALID_ARG, "out of host memory");
+    std::string err = ozemu::build_plan(p->p, format, ms, scaling);
+    if (!err.empty()) {
+        delete p;
+        return fail(OZEMU_ERR_INVALID_ARG, err);
+    }
+    *out = p;
+    return ok();
+}
+
+ozemu_status ozemu_plan_create(ozemu_plan* out, int format, int num_moduli, int scaling) {
+    if (!out) return fail(OZEMU_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (format != OZEMU_INT8) return fail(OZEMU_ERR_UNSUPPORTED, "only OZEMU_INT8 is built");
+    if (num_moduli < 2 || num_moduli > ozemu::kMaxModuli)
+        return fail(OZEMU_ERR_INVALID_ARG, "number of moduli must be in [2, 32]");
+    std::vector<int> ms = ozemu::best_coprime_set(num_moduli, 256);
+    if ((int)ms.size() != num_moduli) return fail(OZEMU_ERR_INVALID_ARG, "no modulus set");
+    std::vector<int32_t> m32(ms.begin(), ms.end());
+    return ozemu_plan_create_moduli(out, format, num_moduli, m32.data(), scaling);
+}
+
+ozemu_status ozemu_plan_destroy(ozemu_plan plan) {
+    delete plan;
+    return ok();
+}
+
+ozemu_status ozemu_plan_moduli(ozemu_plan plan, int32_t* out, int cap, int* count) {
+    if (ozemu_status s = check_plan(plan)) return s;
+    if (!count) return fail(OZEMU_ERR_INVALID_ARG, "count is NULL");
+    *count = plan->p.n;
+    if (out) {
+        if (cap < plan->p.n) return fail(OZEMU_ERR_INVALID_ARG, "capacity too small");
+        for (int i = 0; i < plan->p.n; ++i) out[i] = plan->p.moduli[i];
+    }
+    return ok();
+}
+
+ozemu_status ozemu_plan_kept_bits(ozemu_plan plan, int64_t k, int* beta_a, int* beta_b) {
+    if (ozemu_status s = check_plan(plan)) return s;
+    if (!beta_a || !beta_b) return fail(OZEMU_ERR_INVALID_ARG, "NULL output");
+    if (plan->p.scaling == OZEMU_SCALE_BOUND)
+        return fail(OZEMU_ERR_UNSUPPORTED, "bound mode decides bits per row and column");
+    if (ozemu_status s = check_shape(plan->p, 1, 1, k)) return s;
+    kept_bits_of(plan->p, k, *beta_a, *beta_b);
+    return ok();
+}
+
+ozemu_status ozemu_plan_k_max(ozemu_plan plan, int64_t* k_max) {
+    if (ozemu_status s = check_plan(plan)) return s;
+    if (!k_max) return fail(OZEMU_ERR_INVALID_ARG, "NULL output");
+    int64_t km = plan->p.kappa_acc;
+    if (plan->p.scaling == OZEMU_SCALE_F53) {
+        // largest k with the window at 53 bits, by bisection on the exact test
+        int64_t lo = 0, hi = km;
+        while (lo < hi) {
+            int64_t mid = lo + (hi - lo + 1) / 2;
+            if (ozemu::window_holds(plan->p, mid, 53, 53))
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        km = lo;
+    } else if (plan->p.scaling == OZEMU_SCALE_BOUND && km > 524287) {
+        km = 524287;
+    }
+    *k_max = km;
+    return ok();
+}
+
+ozemu_status ozemu_plane_dims(ozemu_plan plan, int64_t m, int64_t n, int64_t k, int64_t* m_pad,
+                              int64_t* n_pad, int64_t* k_pad) {
+    if (ozemu_status s = check_plan(plan)) return s;
+    if (m < 0 || n < 0 || k < 0) return fail(OZEMU_ERR_INVALID_ARG, "negative dimension");
+    Dims d = dims_of(m, n, k);
+    if (m_pad) *m_pad = d.m_pad;
+    if (n_pad) *n_pad = d.n_pad;
+    if (k_pad) *k_pad = d.k_pad;
+    return ok();
+}
+
+ozemu_status ozemu_workspace_size(ozemu_plan plan, int64_t m, int64_t n, int64_t k,
+                                  size_t* bytes) {
+    if (ozemu_status s = check_plan(plan)) return s;
+    if (!bytes) return fail(OZEMU_ERR_INVALID_ARG, "bytes is NULL");
+    if (m < 0 || n < 0 || k < 0) return fail(OZEMU_ERR_INVALID_ARG, "negative dimension");
+    *bytes = layout_of(plan->p, m, n, k).total;
+    return ok();
+}
+
+ozemu_status ozemu_scale(ozemu_plan plan, void* stream, int64_t m, int64_t n, int64_t k,
+                         const double* A, int64_t lda, const double* B, int64_t ldb,
+                         int32_t* shift_a, int32_t* shift_b, void* workspace, size_t ws_bytes) {
+    if (ozemu_status s = check_plan(plan)) return s;
+    const ozemu::Plan& p = plan->p;
+    if (ozemu_status s = check_shape(p, m, n, k)) return s;
+    if (ozemu_status s = check_operands(m, n, k, A, lda, B, ldb)) return s;
+    if ((m > 0 && !shift_a) || (n > 0 && !shift_b))
+        return fail(OZEMU_ERR_INVALID_ARG, "shift output is NULL");
+    const size_t need = scale_ws_need(p, m, n, k);
+    if (need > 0 && (!workspace || ws_bytes < need))
+        return fail(OZEMU_ERR_WORKSPACE, "workspace smaller than ozemu_workspace_size");
+    if (m == 0 && n == 0) return ok();
+    return run_scale(p, (hipStream_t)stream, m, n, k, A, lda, B, ldb, shift_a, shift_b,
+                     (char*)workspace);
+}
+
+ozemu_status ozemu_reduce(ozemu_plan plan, void* stream, int64_t m, int64_t n, int64_t k,
+                          const double* A, int64_t lda, const double* B, int64_t ldb,
+                          const int32_t* shift_a, const int32_t* shift_b, int8_t* planes_a,
+                          int8_t* planes_b) {
+    if (ozemu_status s = check_plan(plan)) return s;
+    const ozemu::Plan& p = plan->p;
+    if (ozemu_status s = check_shape(p, m, n, k)) return s;
+    if (ozemu_status s = check_operands(m, n, k, A, lda, B, ldb)) return s;
+    Dims d = dims_of(m, n, k);
+    hipStream_t st = (hipStream_t)stream;
+    if (d.m_pad > 0 && d.k_pad > 0) {
+        if (!planes_a || !shift_a) return fail(OZEMU_ERR_INVALID_ARG, "planes_a or shift_a is NULL");
+        if (ozemu_status s = hip_check(ozemu::launch_encode_a(st, p.mod, m, k, A, lda, shift_a,
+                                                              d.m_pad, d.k_pad, planes_a),
+                                       "encode_a"))
+            return s;
+    }
+    if (d.n_pad > 0 && d.k_pad > 0) {
+        if (!planes_b || !shift_b) return fail(OZEMU_ERR_INVALID_ARG, "planes_b or shift_b is NULL");
+        if (ozemu_status s = hip_check(ozemu::launch_encode_b(st, p.mod, k, n, B, ldb, shift_b,
+                                                              d.n_pad, d.k_pad, planes_b),
+                                       "encode_b"))
+            return s;
+    }
+    return ok();
+}
+
+ozemu_status ozemu_residue_gemm(ozemu_plan plan, void* stream, int64_t m, int64_t n, int64_t k,
+                                const int8_t* planes_a, const int8_t* planes_b,
+                                uint8_t* residues) {
+    if (ozemu_status s = check_plan(plan)) return s;
+    const ozemu::Plan& p = plan->p;
+    if (ozemu_status s = check_shape(p, m, n, k)) return s;
+    Dims d = dims_of(m, n, k);
+    if (d.m_pad == 0 || d.n_pad == 0) return ok();
+    if (!residues) return fail(OZEMU_ERR_INVALID_ARG, "residues is NULL");
+    if (d.k_pad > 0 && (!planes_a || !planes_b))
+        return fail(OZEMU_ERR_INVALID_ARG, "planes are NULL");
+    if (d.k_pad == 0) {
+        return hip_check(ozemu::launch_fill_i32((hipStream_t)stream,
+                                                (int64_t)p.n * d.m_pad * d.n_pad / 4, 0,
+                                                reinterpret_cast<int32_t*>(residues)),
+                         "zero residues");
+    }
+    return hip_check(ozemu::launch_residue_gemm((hipStream_t)stream, p.mod, d.m_pad, d.n_pad,
+                                                d.k_pad, planes_a, planes_b, residues),
+                     "residue_gemm");
+}
+
+ozemu_status ozemu_reconstruct(ozemu_plan plan, void* stream, int64_t m, int64_t n, int64_t k,
+                               const uint8_t* residues, const int32_t* shift_a,
+                               const int32_t* shift_b, double* C, int64_t ldc) {
+    if (ozemu_status s = check_plan(plan)) return s;
+    const ozemu::Plan& p = plan->p;
+    if (ozemu_status s = check_shape(p, m, n, k)) return s;
+    if (m == 0 || n == 0) return ok();
+    if (!C || ldc < n) return fail(OZEMU_ERR_INVALID_ARG, "C is NULL or ldc < n");
+    if (!residues || !shift_a || !shift_b)
+        return fail(OZEMU_ERR_INVALID_ARG, "residues or shifts are NULL");
+    Dims d = dims_of(m, n, k);
+    return hip_check(ozemu::launch_reconstruct((hipStream_t)stream, p.crt, m, n, d.m_pad, d.n_pad,
+                                               residues, shift_a, shift_b, C, ldc),
+                     "reconstruct");
+}
+
+ozemu_status ozemu_dgemm(ozemu_plan plan, void* stream, int64_t m, int64_t n, int64_t k,
+                         const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
+                         int64_t ldc, void* workspace, size_t ws_bytes) {
+    if (ozemu_status s = check_plan(plan)) return s;
+    const ozemu::Plan& p = plan->p;
+    if (ozemu_status s = check_shape(p, m, n, k)) return s;
+    if (m == 0 || n == 0) return ok();
+    if (ozemu_status s = check_operands(m, n, k, A, lda, B, ldb)) return s;
+    if (!C || ldc < n) return fail(OZEMU_ERR_INVALID_ARG, "C is NULL or ldc < n");
+    hipStream_t st = (hipStream_t)stream;
+    if (k == 0) return hip_check(ozemu::launch_zero_c(st, m, n, C, ldc), "zero C");
+    Layout L = layout_of(p, m, n, k);
+    if (!workspace || ws_bytes < L.total)
+        return fail(OZEMU_ERR_WORKSPACE, "workspace smaller than ozemu_workspace_size");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255)
+        return fail(OZEMU_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+    char* ws = static_cast<char*>(workspace);
+    int32_t* sa = reinterpret_cast<int32_t*>(ws + L.shift_a);
+    int32_t* sb = reinterpret_cast<int32_t*>(ws + L.shift_b);
+    int8_t* pa = reinterpret_cast<int8_t*>(ws + L.planes_a);
+    int8_t* pb = reinterpret_cast<int8_t*>(ws + L.planes_b);
+    uint8_t* z = reinterpret_cast<uint8_t*>(ws + L.residues);
+    Dims d = dims_of(m, n, k);
+    if (ozemu_status s = run_scale(p, st, m, n, k, A, lda, B, ldb, sa, sb, ws)) return s;
+    if (ozemu_status s = hip_check(
+            ozemu::launch_encode_a(st, p.mod, m, k, A, lda, sa, d.m_pad, d.k_pad, pa), "encode_a"))
+        return s;
+    if (ozemu_status s = hip_check(
+            ozemu::launch_encode_b(st, p.mod, k, n, B, ldb, sb, d.n_pad, d.k_pad, pb), "encode_b"))
+        return s;
+    if (ozemu_status s = hip_check(
+            ozemu::launch_residue_gemm(st, p.mod, d.m_pad, d.n_pad, d.k_pad, pa, pb, z),
+            "residue_gemm"))
+        return s;
+    return hip_check(ozemu::launch_reconstruct(st, p.crt, m, n, d.m_pad, d.n_pad, z, sa, sb, C, ldc),
+                     "reconstruct");
+}
+
+}  // extern "C"

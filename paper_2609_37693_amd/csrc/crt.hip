@@ -1,0 +1,204 @@
+// Reconstruct (Sec. V-A phase 5, Sec. V-C "Reconstruct"): for each output
+// entry, the balanced CRT solution X of its residues, then one rounding of
+// X 2^-(s_i + t_j) into FP64.
+//
+// CRT sum in digits whose sums stay exact: with u_l = (z_l inv_l) mod m_l,
+// S = sum_l u_l M_l is accumulated per 32-bit digit in 64-bit integers (each
+// term below 2^40, at most 32 terms). S / P = sum_l u_l / m_l exactly, so one
+// FP64 estimate q = rint(sum_l u_l / m_l) of the nearest multiple of P gives
+// X = S - q P, exact in the same digits. When the estimate is off by one
+// (only possible when |X| is within a few ulps of P / 2), |X| exceeds
+// (P - 1) / 2 and the exact fallback replaces |X| by P - |X| with the sign
+// flipped. The magnitude is then rounded once, to nearest even, at the bit
+// that lands on 2^-1074 or on the 53rd significant bit, whichever is higher,
+// and scaled by an exact ldexp; overflow gives an infinity.
+#include "ozemu_internal.hpp"
+
+namespace ozemu {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kPerThread = 4;  // consecutive output columns per thread
+
+// Finishes one entry from its digit sums acc = sum_l u_l M_l and the
+// estimate f = sum_l u_l / m_l.
+template <int D>
+__device__ __forceinline__ double finish_one(const CrtConsts& cc, int64_t* acc, double f, int sc) {
+    const int64_t q = (int64_t)rint(f);
+#pragma unroll
+    for (int d = 0; d < D; ++d) acc[d] -= q * (int64_t)cc.P[d];
+    // carry-normalize into two's complement digits
+    uint32_t x[D];
+    int64_t carry = 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const int64_t v = acc[d] + carry;
+        x[d] = (uint32_t)v;
+        carry = v >> 32;  // arithmetic shift
+    }
+    bool neg = carry < 0;
+    if (neg) {  // magnitude = -X
+        uint64_t c = 1;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const uint64_t v = (uint64_t)(~x[d]) + c;
+            x[d] = (uint32_t)v;
+            c = v >> 32;
+        }
+    }
+    // exact fallback: |X| > (P - 1) / 2  =>  |X| <- P - |X|, sign flipped
+    int cmp = 0;
+#pragma unroll
+    for (int d = D - 1; d >= 0; --d)
+        if (cmp == 0 && x[d] != cc.half[d]) cmp = (x[d] > cc.half[d]) ? 1 : -1;
+    if (cmp > 0) {
+        int64_t b = 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const int64_t v = (int64_t)cc.P[d] - (int64_t)x[d] - b;
+            b = v < 0;
+            x[d] = (uint32_t)(v + (b ? (1ll << 32) : 0));
+        }
+        neg = !neg;
+    }
+    // bit length
+    int L = 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+        if (x[d] != 0) L = 32 * d + 32 - __clz(x[d]);
+    if (L == 0) return 0.0;
+    int rb = L - 53;
+    if (sc - 1074 > rb) rb = sc - 1074;
+    double r;
+    if (rb <= 0) {
+        const uint64_t t = (uint64_t)x[0] | ((uint64_t)x[1] << 32);  // L <= 53
+        r = ldexp((double)t, -sc);
+    } else {
+        uint64_t t = 0;
+        bool half = false, sticky = false;
+        const int hb = rb - 1;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const int off = 32 * d - rb;
+            const uint64_t v = x[d];
+            if (off >= 0 && off < 64)
+                t |= v << off;
+            else if (off < 0 && off > -32)
+                t |= v >> (-off);
+            const int lo = 32 * d;
+            if (hb >= lo && hb < lo + 32) half = (x[d] >> (hb - lo)) & 1u;
+            if (lo + 32 <= hb)
+                sticky |= (x[d] != 0);
+            else if (lo < hb)
+                sticky |= (x[d] & ((1u << (hb - lo)) - 1u)) != 0;
+        }
+        if (half && (sticky || (t & 1))) t += 1;
+        r = ldexp((double)t, rb - sc);
+    }
+    return neg ? -r : r;
+}
+
+template <int D>
+__global__ __launch_bounds__(kThreads) void reconstruct_kernel(CrtConsts cc, int64_t m, int64_t n,
+                                                               int64_t m_pad, int64_t n_pad,
+                                                               const uint8_t* __restrict__ Z,
+                                                               const int32_t* __restrict__ sa,
+                                                               const int32_t* __restrict__ sb,
+                                                               double* __restrict__ C, int64_t ldc) {
+    const int64_t per_row = (n + kPerThread - 1) / kPerThread;
+    const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (g >= m * per_row) return;
+    const int64_t i = g / per_row;
+    const int64_t j0 = (g % per_row) * kPerThread;
+    const int64_t plane = m_pad * n_pad;
+    int64_t acc[kPerThread][D];
+    double f[kPerThread];
+#pragma unroll
+    for (int c = 0; c < kPerThread; ++c) {
+        f[c] = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) acc[c][d] = 0;
+    }
+    const uint8_t* zp = Z + i * n_pad + j0;
+    for (int l = 0; l < cc.n; ++l) {
+        const uint32_t word = *reinterpret_cast<const uint32_t*>(zp + (int64_t)l * plane);
+        const uint32_t ml = cc.m[l], mu = cc.mu[l], inv = cc.inv[l];
+        const double rcp = cc.rcp[l];
+#pragma unroll
+        for (int c = 0; c < kPerThread; ++c) {
+            const uint64_t u = barrett32(((word >> (8 * c)) & 0xFFu) * inv, ml, mu);
+            f[c] += (double)u * rcp;
+#pragma unroll
+            for (int d = 0; d < D; ++d) acc[c][d] += (int64_t)(u * cc.Ml[l][d]);
+        }
+    }
+    const int32_t si = sa[i];
+    double out[kPerThread];
+#pragma unroll
+    for (int c = 0; c < kPerThread; ++c) {
+        const int64_t j = j0 + c;
+        out[c] = 0.0;
+        if (j >= n) continue;
+        const int32_t tj = sb[j];
+        if (si == kShiftNonFinite || tj == kShiftNonFinite)
+            out[c] = __builtin_nan("");
+        else
+            out[c] = finish_one<D>(cc, acc[c], f[c], si + tj);
+    }
+    double* crow = C + i * ldc + j0;
+    if (j0 + kPerThread <= n && ((reinterpret_cast<uintptr_t>(crow) & 15) == 0)) {
+        reinterpret_cast<double2*>(crow)[0] = make_double2(out[0], out[1]);
+        reinterpret_cast<double2*>(crow)[1] = make_double2(out[2], out[3]);
+    } else {
+        for (int c = 0; c < kPerThread; ++c)
+            if (j0 + c < n) crow[c] = out[c];
+    }
+}
+
+__global__ void zero_c_kernel(int64_t m, int64_t n, double* C, int64_t ldc) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= m * n) return;
+    C[(g / n) * ldc + g % n] = 0.0;
+}
+
+template <int D>
+hipError_t launch_d(hipStream_t st, const CrtConsts& cc, int64_t m, int64_t n, int64_t m_pad,
+                    int64_t n_pad, const uint8_t* Z, const int32_t* sa, const int32_t* sb,
+                    double* C, int64_t ldc) {
+    const int64_t threads = m * ((n + kPerThread - 1) / kPerThread);
+    const int64_t blocks = (threads + kThreads - 1) / kThreads;
+    reconstruct_kernel<D><<<dim3((unsigned)blocks), dim3(kThreads), 0, st>>>(cc, m, n, m_pad, n_pad,
+                                                                             Z, sa, sb, C, ldc);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_reconstruct(hipStream_t st, const CrtConsts& cc, int64_t m, int64_t n,
+                              int64_t m_pad, int64_t n_pad, const uint8_t* residues,
+                              const int32_t* shift_a, const int32_t* shift_b, double* C,
+                              int64_t ldc) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    switch (cc.d) {
+        case 2: return launch_d<2>(st, cc, m, n, m_pad, n_pad, residues, shift_a, shift_b, C, ldc);
+        case 3: return launch_d<3>(st, cc, m, n, m_pad, n_pad, residues, shift_a, shift_b, C, ldc);
+        case 4: return launch_d<4>(st, cc, m, n, m_pad, n_pad, residues, shift_a, shift_b, C, ldc);
+        case 5: return launch_d<5>(st, cc, m, n, m_pad, n_pad, residues, shift_a, shift_b, C, ldc);
+        case 6: return launch_d<6>(st, cc, m, n, m_pad, n_pad, residues, shift_a, shift_b, C, ldc);
+        case 7: return launch_d<7>(st, cc, m, n, m_pad, n_pad, residues, shift_a, shift_b, C, ldc);
+        case 8: return launch_d<8>(st, cc, m, n, m_pad, n_pad, residues, shift_a, shift_b, C, ldc);
+        case 9: return launch_d<9>(st, cc, m, n, m_pad, n_pad, residues, shift_a, shift_b, C, ldc);
+        case 10: return launch_d<10>(st, cc, m, n, m_pad, n_pad, residues, shift_a, shift_b, C, ldc);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_zero_c(hipStream_t st, int64_t m, int64_t n, double* C, int64_t ldc) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    const int64_t total = m * n;
+    zero_c_kernel<<<dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st>>>(m, n, C, ldc);
+    return hipGetLastError();
+}
+
+}  // namespace ozemu

@@ -1,0 +1,161 @@
+// Reduce phase (Sec. V-A phase 2, Sec. V-C "Reduce"): applies Scale's shifts,
+// truncates each entry (eq. "convert") without storing A' or B', and writes
+// its balanced residue modulo every modulus of the plan as int8 (two's
+// complement) into the residue planes. Each FP64 entry is read once; all
+// moduli are produced from registers.
+//
+// Planes of A keep A's row-major order ([l][i][h], K-contiguous). Planes of
+// B are written transposed ([l][j][h]) so the GEMM reads both operands
+// K-contiguous; the transpose goes through LDS.
+#include "ozemu_internal.hpp"
+
+namespace ozemu {
+
+namespace {
+
+constexpr int kEncThreads = 256;
+constexpr int kEncVec = 16;  // consecutive k entries per thread (one 16-byte store per modulus)
+
+struct Entry {
+    uint64_t mant;  // |x| = mant 2^ex
+    int sh;         // ex + shift: the truncated magnitude is mant 2^sh
+    bool neg;
+};
+
+__device__ __forceinline__ Entry make_entry(double x, int32_t shift) {
+    Entry e;
+    uint64_t bits = (uint64_t)__double_as_longlong(x);
+    uint64_t a = bits & 0x7FFFFFFFFFFFFFFFull;
+    e.neg = (bits >> 63) != 0;
+    if (a >= 0x7FF0000000000000ull || shift == kShiftNonFinite) a = 0;  // non-finite: zero row
+    int ex;
+    split_double(a, e.mant, ex);
+    e.sh = ex + shift;
+    if (e.mant == 0) e.sh = 0;
+    return e;
+}
+
+__device__ __forceinline__ uint32_t pack4(const int8_t* v) {
+    return (uint32_t)(uint8_t)v[0] | ((uint32_t)(uint8_t)v[1] << 8) |
+           ((uint32_t)(uint8_t)v[2] << 16) | ((uint32_t)(uint8_t)v[3] << 24);
+}
+
+// grid: (m_pad, ceil(k_pad / (kEncThreads * kEncVec))). Thread handles
+// columns [h, h + 16) of row i.
+__global__ __launch_bounds__(kEncThreads) void encode_a_kernel(ModConsts mc, int64_t m, int64_t k,
+                                                               const double* A, int64_t lda,
+                                                               const int32_t* shift_a,
+                                                               int64_t m_pad, int64_t k_pad,
+                                                               int8_t* planes) {
+    const int64_t i = blockIdx.x;
+    const int64_t h = ((int64_t)blockIdx.y * kEncThreads + threadIdx.x) * kEncVec;
+    if (h >= k_pad) return;
+    Entry ent[kEncVec];
+    const int32_t s = (i < m) ? shift_a[i] : 0;
+    const double* row = A + i * lda;
+    if (i < m && h + kEncVec <= k && ((reinterpret_cast<uintptr_t>(row + h) & 15) == 0)) {
+        const double2* p2 = reinterpret_cast<const double2*>(row + h);
+#pragma unroll
+        for (int q = 0; q < kEncVec / 2; ++q) {
+            double2 v = p2[q];
+            ent[2 * q] = make_entry(v.x, s);
+            ent[2 * q + 1] = make_entry(v.y, s);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < kEncVec; ++q) {
+            double v = (i < m && h + q < k) ? row[h + q] : 0.0;
+            ent[q] = make_entry(v, s);
+        }
+    }
+    const int64_t plane_stride = m_pad * k_pad;
+    int8_t* out = planes + i * k_pad + h;
+    for (int l = 0; l < mc.n; ++l) {
+        const uint32_t mm = mc.m[l], mu = mc.mu[l], c32 = mc.c32[l], c16 = mc.c16[l];
+        int8_t r[kEncVec];
+#pragma unroll
+        for (int q = 0; q < kEncVec; ++q)
+            r[q] = balanced_i8(trunc_residue(ent[q].mant, ent[q].sh, mm, mu, c32, c16), ent[q].neg, mm);
+        uint4 w;
+        w.x = pack4(r);
+        w.y = pack4(r + 4);
+        w.z = pack4(r + 8);
+        w.w = pack4(r + 12);
+        *reinterpret_cast<uint4*>(out + (int64_t)l * plane_stride) = w;
+    }
+}
+
+// grid: (n_pad / 64, k_pad / 64). A 64 (k) x 64 (n) tile of B: thread t
+// reads column j = t % 64 at rows 16 * (t / 64) .. + 15 (coalesced along j),
+// builds the 16 residues of that column segment per modulus, stores them as
+// one 16-byte word into LDS row j, and the tile is written out row by row
+// (64 K-contiguous bytes per column of B).
+constexpr int kTB = 64;
+constexpr int kLdsRow = kTB + 16;  // bytes; padding spreads rows over banks
+
+__global__ __launch_bounds__(kEncThreads) void encode_b_kernel(ModConsts mc, int64_t k, int64_t n,
+                                                               const double* B, int64_t ldb,
+                                                               const int32_t* shift_b,
+                                                               int64_t n_pad, int64_t k_pad,
+                                                               int8_t* planes) {
+    __shared__ __align__(16) int8_t tile[kTB * kLdsRow];
+    const int64_t j0 = (int64_t)blockIdx.x * kTB;
+    const int64_t h0 = (int64_t)blockIdx.y * kTB;
+    const int tj = threadIdx.x & 63;
+    const int hq = threadIdx.x >> 6;  // 0..3
+    const int64_t j = j0 + tj;
+    const int32_t s = (j < n) ? shift_b[j] : 0;
+    Entry ent[kEncVec];
+#pragma unroll
+    for (int q = 0; q < kEncVec; ++q) {
+        const int64_t h = h0 + hq * kEncVec + q;
+        double v = (j < n && h < k) ? B[h * ldb + j] : 0.0;
+        ent[q] = make_entry(v, s);
+    }
+    const int64_t plane_stride = n_pad * k_pad;
+    const int orow = threadIdx.x >> 2;    // output column of B (row of the plane)
+    const int ochunk = threadIdx.x & 3;   // 16-byte chunk of K
+    for (int l = 0; l < mc.n; ++l) {
+        const uint32_t mm = mc.m[l], mu = mc.mu[l], c32 = mc.c32[l], c16 = mc.c16[l];
+        int8_t r[kEncVec];
+#pragma unroll
+        for (int q = 0; q < kEncVec; ++q)
+            r[q] = balanced_i8(trunc_residue(ent[q].mant, ent[q].sh, mm, mu, c32, c16), ent[q].neg, mm);
+        uint4 w;
+        w.x = pack4(r);
+        w.y = pack4(r + 4);
+        w.z = pack4(r + 8);
+        w.w = pack4(r + 12);
+        if (l > 0) __syncthreads();  // previous modulus fully copied out
+        *reinterpret_cast<uint4*>(tile + tj * kLdsRow + hq * kEncVec) = w;
+        __syncthreads();
+        uint4 o = *reinterpret_cast<const uint4*>(tile + orow * kLdsRow + ochunk * kEncVec);
+        *reinterpret_cast<uint4*>(planes + (int64_t)l * plane_stride + (j0 + orow) * k_pad + h0 +
+                                  ochunk * kEncVec) = o;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_encode_a(hipStream_t st, const ModConsts& mc, int64_t m, int64_t k,
+                           const double* A, int64_t lda, const int32_t* shift_a, int64_t m_pad,
+                           int64_t k_pad, int8_t* planes_a) {
+    if (m_pad <= 0 || k_pad <= 0) return hipSuccess;
+    const int64_t per_block = (int64_t)kEncThreads * kEncVec;
+    dim3 grid((unsigned)m_pad, (unsigned)((k_pad + per_block - 1) / per_block));
+    encode_a_kernel<<<grid, dim3(kEncThreads), 0, st>>>(mc, m, k, A, lda, shift_a, m_pad, k_pad,
+                                                        planes_a);
+    return hipGetLastError();
+}
+
+hipError_t launch_encode_b(hipStream_t st, const ModConsts& mc, int64_t k, int64_t n,
+                           const double* B, int64_t ldb, const int32_t* shift_b, int64_t n_pad,
+                           int64_t k_pad, int8_t* planes_b) {
+    if (n_pad <= 0 || k_pad <= 0) return hipSuccess;
+    dim3 grid((unsigned)(n_pad / kTB), (unsigned)(k_pad / kTB));
+    encode_b_kernel<<<grid, dim3(kEncThreads), 0, st>>>(mc, k, n, B, ldb, shift_b, n_pad, k_pad,
+                                                        planes_b);
+    return hipGetLastError();
+}
+
+}  // namespace ozemu

@@ -1,0 +1,175 @@
+// Internal definitions shared by the host plan code and the HIP kernels of
+// libozemu: launch-argument structs, tile sizes, and the integer helpers the
+// kernels use (Barrett reduction, IEEE-754 field extraction).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ozemu {
+
+constexpr int kMaxModuli = 32;  // moduli per plan
+constexpr int kMaxDigits = 10;  // 32-bit digits of CRT sums: N * P < 2^(8*32 + 5)
+constexpr int kBetaCap = 127;   // largest kept-bit count of any mode
+
+// Residue GEMM tiling. Planes are padded to whole tiles, so the GEMM kernel
+// needs no bounds checks; padding entries are zero.
+constexpr int kTileM = 256;
+constexpr int kTileN = 256;
+constexpr int kTileK = 64;
+
+// Row/column key for the exponent scan: frexp exponent of the largest
+// magnitude, or these sentinels.
+constexpr int32_t kKeyZero = INT32_MIN + 1;
+constexpr int32_t kKeyNonFinite = INT32_MAX;
+constexpr int32_t kShiftNonFinite = INT32_MIN;
+
+// Per-modulus constants for reduction (Barrett with mu = floor(2^32 / m),
+// one correction step) passed by value as a kernel argument.
+struct ModConsts {
+    int n;
+    uint32_t m[kMaxModuli];
+    uint32_t mu[kMaxModuli];
+    uint32_t c32[kMaxModuli];  // 2^32 mod m
+    uint32_t c16[kMaxModuli];  // 2^16 mod m
+};
+
+// CRT constants: X = sum_l u_l M_l - q P with u_l = (z_l * inv_l) mod m_l,
+// M_l = P / m_l, inv_l = M_l^-1 mod m_l; digits little-endian, 32 bits each.
+struct CrtConsts {
+    int n;
+    int d;  // digits used
+    uint32_t m[kMaxModuli];
+    uint32_t mu[kMaxModuli];
+    uint32_t inv[kMaxModuli];
+    double rcp[kMaxModuli];  // 1 / m_l rounded to FP64
+    uint32_t Ml[kMaxModuli][kMaxDigits];
+    uint32_t P[kMaxDigits];
+    uint32_t half[kMaxDigits];  // floor((P - 1) / 2)
+};
+
+// x mod m for x < 2^32, m in [2, 2^16]; mu = floor(2^32 / m).
+__host__ __device__ __forceinline__ uint32_t barrett32(uint32_t x, uint32_t m, uint32_t mu) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint32_t q = __umulhi(x, mu);
+#else
+    uint32_t q = (uint32_t)(((uint64_t)x * mu) >> 32);
+#endif
+    uint32_t r = x - q * m;
+    return r >= m ? r - m : r;
+}
+
+// v mod m for v < 2^53, m <= 256: with v = a 2^32 + b 2^16 + c the sum
+// a (2^32 mod m) + b (2^16 mod m) + c is below 2^21 2^8 + 2^16 2^8 + 2^16
+// < 2^30, so one Barrett step finishes the reduction.
+__host__ __device__ __forceinline__ uint32_t mod53(uint64_t v, uint32_t m, uint32_t mu, uint32_t c32,
+                                                  uint32_t c16) {
+    uint32_t a = (uint32_t)(v >> 32);  // < 2^21
+    uint32_t lo = (uint32_t)v;
+    uint32_t t = a * c32 + (lo >> 16) * c16 + (lo & 0xFFFFu);
+    return barrett32(t, m, mu);
+}
+
+// 2^e mod m for 0 <= e, by square and multiply (values < 2^16).
+__host__ __device__ __forceinline__ uint32_t pow2mod(int e, uint32_t m, uint32_t mu) {
+    uint32_t r = 1 % m, b = 2 % m;
+    while (e > 0) {
+        if (e & 1) r = barrett32(r * b, m, mu);
+        b = barrett32(b * b, m, mu);
+        e >>= 1;
+    }
+    return r;
+}
+
+// Magnitude of a finite double as integer significand times a power of two:
+// |x| = mant * 2^ex, mant < 2^53 (0 for zero).
+__host__ __device__ __forceinline__ void split_double(uint64_t bits, uint64_t& mant, int& ex) {
+    uint32_t be = (uint32_t)((bits >> 52) & 0x7FF);
+    uint64_t frac = bits & 0x000FFFFFFFFFFFFFull;
+    if (be == 0) {
+        mant = frac;
+        ex = -1074;
+    } else {
+        mant = frac | (1ull << 52);
+        ex = (int)be - 1075;
+    }
+}
+
+// frexp exponent e of a finite nonzero magnitude: 2^(e-1) <= |x| < 2^e.
+__host__ __device__ __forceinline__ int frexp_exponent(uint64_t absbits) {
+    uint32_t be = (uint32_t)(absbits >> 52);
+    if (be != 0) return (int)be - 1022;
+#if defined(__HIP_DEVICE_COMPILE__)
+    int lz = __clzll((long long)absbits);
+#else
+    int lz = __builtin_clzll(absbits);
+#endif
+    return (64 - lz) - 1074;
+}
+
+// Row/column key of one entry (see kKeyZero, kKeyNonFinite).
+__host__ __device__ __forceinline__ int32_t entry_key(uint64_t bits) {
+    uint64_t a = bits & 0x7FFFFFFFFFFFFFFFull;
+    if (a >= 0x7FF0000000000000ull) return kKeyNonFinite;
+    if (a == 0) return kKeyZero;
+    return frexp_exponent(a);
+}
+
+// Balanced residue in two's complement int8 of the integer sign * |v| where
+// r = |v| mod m: representatives [-floor(m/2), ceil(m/2) - 1].
+__host__ __device__ __forceinline__ int8_t balanced_i8(uint32_t r, bool neg, uint32_t m) {
+    if (neg && r != 0) r = m - r;
+    int32_t v = (r >= (m + 1) / 2) ? (int32_t)r - (int32_t)m : (int32_t)r;
+    return (int8_t)v;
+}
+
+// Residue of trunc(x * 2^s) modulo m for a finite double x, in [0, m), with
+// the sign returned separately. Writing |x| = mant * 2^ex, the truncated
+// magnitude is mant >> (-(ex + s)) when ex + s <= 0 (a 53-bit integer), else
+// mant * 2^(ex + s), whose residue is (mant mod m)(2^(ex+s) mod m) mod m.
+__host__ __device__ __forceinline__ uint32_t trunc_residue(uint64_t mant, int sh, uint32_t m,
+                                                          uint32_t mu, uint32_t c32, uint32_t c16) {
+    if (sh <= 0) {
+        uint64_t v = (sh <= -64) ? 0 : (mant >> (-sh));
+        return mod53(v, m, mu, c32, c16);
+    }
+    uint32_t r0 = mod53(mant, m, mu, c32, c16);
+    return barrett32(r0 * pow2mod(sh, m, mu), m, mu);
+}
+
+// Launchers (defined in the .hip files). All take the caller's stream and
+// return hipSuccess or the launch error.
+hipError_t launch_scale_rows(hipStream_t st, int64_t m, int64_t k, const double* A, int64_t lda,
+                             int32_t* key_a);
+hipError_t launch_scale_cols(hipStream_t st, int64_t k, int64_t n, const double* B, int64_t ldb,
+                             int32_t* key_b);
+hipError_t launch_keys_to_shifts(hipStream_t st, int64_t count, int32_t* key_to_shift, int beta,
+                                 const int32_t* beta_per_entry);
+hipError_t launch_encode_a(hipStream_t st, const ModConsts& mc, int64_t m, int64_t k,
+                           const double* A, int64_t lda, const int32_t* shift_a, int64_t m_pad,
+                           int64_t k_pad, int8_t* planes_a);
+hipError_t launch_encode_b(hipStream_t st, const ModConsts& mc, int64_t k, int64_t n,
+                           const double* B, int64_t ldb, const int32_t* shift_b, int64_t n_pad,
+                           int64_t k_pad, int8_t* planes_b);
+hipError_t launch_residue_gemm(hipStream_t st, const ModConsts& mc, int64_t m_pad, int64_t n_pad,
+                               int64_t k_pad, const int8_t* planes_a, const int8_t* planes_b,
+                               uint8_t* residues);
+hipError_t launch_bound_gemm(hipStream_t st, int64_t m_pad, int64_t n_pad, int64_t k_pad,
+                             const int8_t* bar_a, const int8_t* bar_b, int32_t* gmax_a,
+                             int32_t* gmax_b);
+hipError_t launch_bound_planes_a(hipStream_t st, int64_t m, int64_t k, const double* A,
+                                 int64_t lda, const int32_t* key_a, int64_t m_pad, int64_t k_pad,
+                                 int8_t* bar_a);
+hipError_t launch_bound_planes_b(hipStream_t st, int64_t k, int64_t n, const double* B,
+                                 int64_t ldb, const int32_t* key_b, int64_t n_pad, int64_t k_pad,
+                                 int8_t* bar_b);
+hipError_t launch_bound_shifts(hipStream_t st, int64_t count, const int32_t* key,
+                               const int32_t* gmax, int L, int32_t* shift);
+hipError_t launch_fill_i32(hipStream_t st, int64_t count, int32_t value, int32_t* out);
+hipError_t launch_reconstruct(hipStream_t st, const CrtConsts& cc, int64_t m, int64_t n,
+                              int64_t m_pad, int64_t n_pad, const uint8_t* residues,
+                              const int32_t* shift_a, const int32_t* shift_b, double* C,
+                              int64_t ldc);
+hipError_t launch_zero_c(hipStream_t st, int64_t m, int64_t n, double* C, int64_t ldc);
+
+}  // namespace ozemu

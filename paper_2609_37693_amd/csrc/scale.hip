@@ -1,0 +1,227 @@
+// Scale phase (Sec. V-A phase 1; Sec. II-A): one exponent per row of A and
+// per column of B. HBM-bound: every entry is read once, as its IEEE bits.
+//
+// The key of a row is the frexp exponent of its largest magnitude, which is
+// the largest frexp exponent of its entries, so rows reduce with an integer
+// max (kKeyZero for a zero row, kKeyNonFinite if a NaN or infinity occurs).
+// Columns of the row-major B are reduced over slabs of rows with an atomic
+// max on the key, so the launch fills the chip for any shape.
+#include "ozemu_internal.hpp"
+
+namespace ozemu {
+
+namespace {
+
+constexpr int kScaleThreads = 256;
+
+__device__ __forceinline__ int32_t wave_max(int32_t v) {
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// One workgroup per row; each thread strides the row with 16-byte loads.
+__global__ __launch_bounds__(kScaleThreads) void scale_rows_kernel(int64_t k, const double* A,
+                                                                   int64_t lda, int32_t* key_a) {
+    const int64_t i = blockIdx.x;
+    const double* row = A + i * lda;
+    int32_t key = kKeyZero;
+    const bool vec = ((reinterpret_cast<uintptr_t>(row) & 15) == 0);
+    if (vec) {
+        const int64_t k2 = k / 2;
+        const double2* r2 = reinterpret_cast<const double2*>(row);
+        for (int64_t h = threadIdx.x; h < k2; h += kScaleThreads) {
+            double2 v = r2[h];
+            key = max(key, entry_key(__double_as_longlong(v.x)));
+            key = max(key, entry_key(__double_as_longlong(v.y)));
+        }
+        if ((k & 1) && threadIdx.x == 0) key = max(key, entry_key(__double_as_longlong(row[k - 1])));
+    } else {
+        for (int64_t h = threadIdx.x; h < k; h += kScaleThreads)
+            key = max(key, entry_key(__double_as_longlong(row[h])));
+    }
+    key = wave_max(key);
+    __shared__ int32_t part[kScaleThreads / 64];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = key;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t r = part[0];
+        for (int w = 1; w < kScaleThreads / 64; ++w) r = max(r, part[w]);
+        key_a[i] = r;
+    }
+}
+
+constexpr int kColRows = 64;  // rows of B per workgroup slab
+
+// grid: (ceil(n / 256), ceil(k / kColRows)); key_b pre-filled with kKeyZero.
+__global__ __launch_bounds__(kScaleThreads) void scale_cols_kernel(int64_t k, int64_t n,
+                                                                   const double* B, int64_t ldb,
+                                                                   int32_t* key_b) {
+    const int64_t j = (int64_t)blockIdx.x * kScaleThreads + threadIdx.x;
+    if (j >= n) return;
+    const int64_t h0 = (int64_t)blockIdx.y * kColRows;
+    const int64_t h1 = min(k, h0 + kColRows);
+    int32_t key = kKeyZero;
+    for (int64_t h = h0; h < h1; ++h) key = max(key, entry_key(__double_as_longlong(B[h * ldb + j])));
+    if (key != kKeyZero) atomicMax(key_b + j, key);
+}
+
+__global__ void fill_i32_kernel(int64_t count, int32_t value, int32_t* out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) out[i] = value;
+}
+
+// shift = beta - e for a nonzero row, 0 for a zero row, the non-finite
+// marker otherwise; beta is per entry when beta_per_entry is given.
+__global__ void keys_to_shifts_kernel(int64_t count, int32_t* io, int beta,
+                                      const int32_t* beta_per_entry) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    int32_t key = io[i];
+    int32_t b = beta_per_entry ? beta_per_entry[i] : beta;
+    int32_t s;
+    if (key == kKeyNonFinite)
+        s = kShiftNonFinite;
+    else if (key == kKeyZero)
+        s = 0;
+    else
+        s = b - key;
+    io[i] = s;
+}
+
+// Bound-adaptive mode: abar = ceil(|x| 2^(6 - e)) in [0, 64], computed
+// exactly from the significand; rows (A) and transposed columns (B) are
+// written K-contiguous into zero-padded planes like the residue planes.
+__device__ __forceinline__ int8_t bound_value(uint64_t bits, int32_t key) {
+    uint64_t a = bits & 0x7FFFFFFFFFFFFFFFull;
+    if (a == 0 || a >= 0x7FF0000000000000ull || key == kKeyNonFinite || key == kKeyZero) return 0;
+    uint64_t mant;
+    int ex;
+    split_double(a, mant, ex);
+    int sh = ex + 6 - key;  // |x| 2^(6-e) = mant 2^sh < 64
+    uint64_t v;
+    if (sh >= 0)
+        v = mant << sh;
+    else if (sh <= -64)
+        v = 1;
+    else
+        v = (mant + ((1ull << (-sh)) - 1)) >> (-sh);
+    return (int8_t)v;
+}
+
+__global__ void bound_planes_a_kernel(int64_t m, int64_t k, const double* A, int64_t lda,
+                                      const int32_t* key_a, int64_t k_pad, int8_t* bar_a) {
+    const int64_t i = blockIdx.x;
+    const int64_t h = ((int64_t)blockIdx.y * blockDim.x + threadIdx.x);
+    if (h >= k_pad) return;
+    int8_t v = 0;
+    if (i < m && h < k) v = bound_value(__double_as_longlong(A[i * lda + h]), key_a[i]);
+    bar_a[i * k_pad + h] = v;
+}
+
+// grid (ceil(n_pad/64), ceil(k_pad/64)); transpose through LDS.
+__global__ __launch_bounds__(256) void bound_planes_b_kernel(int64_t k, int64_t n, const double* B,
+                                                            int64_t ldb, const int32_t* key_b,
+                                                            int64_t n_pad, int64_t k_pad,
+                                                            int8_t* bar_b) {
+    __shared__ int8_t tile[64][65];
+    const int64_t j0 = (int64_t)blockIdx.x * 64, h0 = (int64_t)blockIdx.y * 64;
+    const int tj = threadIdx.x & 63, th = threadIdx.x >> 6;
+    for (int r = th; r < 64; r += 4) {
+        int64_t h = h0 + r, j = j0 + tj;
+        int8_t v = 0;
+        if (h < k && j < n) v = bound_value(__double_as_longlong(B[h * ldb + j]), key_b[j]);
+        tile[tj][r] = v;
+    }
+    __syncthreads();
+    for (int r = th; r < 64; r += 4) {
+        int64_t j = j0 + r, h = h0 + tj;
+        if (j < n_pad && h < k_pad) bar_b[j * k_pad + h] = tile[r][tj];
+    }
+}
+
+// sigma = min(cap, floor((L + 12 - ceil(log2 gmax)) / 2)), cap when gmax = 0;
+// the shift is sigma - e (0 for a zero row, the marker for a non-finite one).
+__global__ void bound_shifts_kernel(int64_t count, const int32_t* key, const int32_t* gmax, int L,
+                                    int32_t* shift) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    int32_t kk = key[i];
+    int32_t g = gmax[i];
+    int32_t sigma;
+    if (g <= 0) {
+        sigma = kBetaCap;
+    } else {
+        int c = (g == 1) ? 0 : 32 - __clz((uint32_t)(g - 1));
+        int v = L + 12 - c;
+        sigma = (v >= 0) ? v / 2 : -((-v + 1) / 2);
+        if (sigma > kBetaCap) sigma = kBetaCap;
+    }
+    int32_t s;
+    if (kk == kKeyNonFinite)
+        s = kShiftNonFinite;
+    else if (kk == kKeyZero)
+        s = 0;
+    else
+        s = sigma - kk;
+    shift[i] = s;
+}
+
+}  // namespace
+
+hipError_t launch_scale_rows(hipStream_t st, int64_t m, int64_t k, const double* A, int64_t lda,
+                             int32_t* key_a) {
+    if (m <= 0) return hipSuccess;
+    scale_rows_kernel<<<dim3((unsigned)m), dim3(kScaleThreads), 0, st>>>(k, A, lda, key_a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(hipStream_t st, int64_t count, int32_t value, int32_t* out) {
+    if (count <= 0) return hipSuccess;
+    fill_i32_kernel<<<dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st>>>(count, value, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_cols(hipStream_t st, int64_t k, int64_t n, const double* B, int64_t ldb,
+                             int32_t* key_b) {
+    if (n <= 0) return hipSuccess;
+    hipError_t e = launch_fill_i32(st, n, kKeyZero, key_b);
+    if (e != hipSuccess || k <= 0) return e;
+    dim3 grid((unsigned)((n + kScaleThreads - 1) / kScaleThreads),
+              (unsigned)((k + kColRows - 1) / kColRows));
+    scale_cols_kernel<<<grid, dim3(kScaleThreads), 0, st>>>(k, n, B, ldb, key_b);
+    return hipGetLastError();
+}
+
+hipError_t launch_keys_to_shifts(hipStream_t st, int64_t count, int32_t* io, int beta,
+                                 const int32_t* beta_per_entry) {
+    if (count <= 0) return hipSuccess;
+    keys_to_shifts_kernel<<<dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st>>>(
+        count, io, beta, beta_per_entry);
+    return hipGetLastError();
+}
+
+hipError_t launch_bound_planes_a(hipStream_t st, int64_t m, int64_t k, const double* A,
+                                 int64_t lda, const int32_t* key_a, int64_t m_pad, int64_t k_pad,
+                                 int8_t* bar_a) {
+    dim3 grid((unsigned)m_pad, (unsigned)((k_pad + 255) / 256));
+    bound_planes_a_kernel<<<grid, dim3(256), 0, st>>>(m, k, A, lda, key_a, k_pad, bar_a);
+    return hipGetLastError();
+}
+
+hipError_t launch_bound_planes_b(hipStream_t st, int64_t k, int64_t n, const double* B,
+                                 int64_t ldb, const int32_t* key_b, int64_t n_pad, int64_t k_pad,
+                                 int8_t* bar_b) {
+    dim3 grid((unsigned)((n_pad + 63) / 64), (unsigned)((k_pad + 63) / 64));
+    bound_planes_b_kernel<<<grid, dim3(256), 0, st>>>(k, n, B, ldb, key_b, n_pad, k_pad, bar_b);
+    return hipGetLastError();
+}
+
+hipError_t launch_bound_shifts(hipStream_t st, int64_t count, const int32_t* key,
+                               const int32_t* gmax, int L, int32_t* shift) {
+    if (count <= 0) return hipSuccess;
+    bound_shifts_kernel<<<dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st>>>(count, key,
+                                                                                   gmax, L, shift);
+    return hipGetLastError();
+}
+
+}  // namespace ozemu

@@ -1,0 +1,137 @@
+"""CPU tests of the C-ABI: the library loads, exports every symbol the
+header declares, builds plans on the host, and rejects bad arguments before
+any launch. No compute call runs here (there is no GPU)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from oracle import moduli as md
+from oracle import scheme
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ozemu.h")
+
+oz = pytest.importorskip("paper_2609_37693_amd")
+from paper_2609_37693_amd import _lib  # noqa: E402
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(ozemu_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("ozemu_plan_create", "ozemu_plan_destroy", "ozemu_workspace_size", "ozemu_dgemm",
+                 "ozemu_scale", "ozemu_reduce", "ozemu_residue_gemm", "ozemu_reconstruct",
+                 "ozemu_status_string", "ozemu_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (ozemu_\w+)", out))
+    assert set(_declared()) <= exported
+    # the ctypes table matches the header one to one
+    assert set(_lib.SIGNATURES) == set(_declared())
+
+
+@pytest.mark.parametrize("n", [2, 10, 14, 16, 20, 24, 32])
+def test_default_moduli_match_oracle_search(n):
+    plan = oz.Plan(num_moduli=n, scaling="W")
+    assert plan.moduli() == md.best_coprime_set(n, 256)
+
+
+@pytest.mark.parametrize("n,k", [(10, 256), (14, 256), (14, 8192), (16, 8192), (20, 8192),
+                                 (20, 16384), (32, 1), (12, 131071)])
+def test_window_kept_bits_match_oracle(n, k):
+    plan = oz.Plan(num_moduli=n, scaling="W")
+    P = md.product(plan.moduli())
+    assert plan.kept_bits(k) == scheme.kept_bits("W", P, k)
+
+
+def test_k_max_matches_paper_caps():
+    p256 = oz.Plan(num_moduli=16, scaling="W")
+    assert p256.k_max() == 131071
+    p239 = oz.Plan(moduli=list(md.PAPER_INT8_239_SET), scaling="F53")
+    assert p239.k_max() == 151647
+    B = 2 ** 53 - 1
+    p14 = oz.Plan(num_moduli=15, scaling="F53")
+    assert p14.k_max() == min(md.kappa_rec(md.product(p14.moduli()), B, B), 131071)
+
+
+def test_explicit_moduli_sorted_and_validated():
+    plan = oz.Plan(moduli=[7, 11, 256, 9], scaling="W")
+    assert plan.moduli() == [256, 11, 9, 7]
+    with pytest.raises(oz.OzemuError):
+        oz.Plan(moduli=[6, 9, 11], scaling="W")  # not coprime
+    with pytest.raises(oz.OzemuError):
+        oz.Plan(moduli=[257, 3], scaling="W")
+    with pytest.raises(oz.OzemuError):
+        oz.Plan(num_moduli=1, scaling="W")
+    with pytest.raises(oz.OzemuError):
+        oz.Plan(num_moduli=33, scaling="W")
+
+
+def test_plane_dims_and_workspace():
+    plan = oz.Plan(num_moduli=14, scaling="W")
+    assert plan.plane_dims(256, 256, 256) == (256, 256, 256)
+    assert plan.plane_dims(257, 1, 65) == (512, 256, 128)
+    assert plan.plane_dims(0, 0, 0) == (0, 0, 0)
+    ws = plan.workspace_size(300, 200, 100)
+    mp, np_, kp = 512, 256, 128
+    assert ws >= 14 * (mp * kp + np_ * kp + mp * np_)
+    g = oz.Plan(num_moduli=14, scaling="G")
+    assert g.workspace_size(300, 200, 100) > ws
+
+
+def _call_dgemm(plan, m, n, k, A=1, lda=None, B=1, ldb=None, C_=1, ldc=None, ws=None,
+                ws_bytes=0):
+    lib = _lib.load()
+    p = lambda v: C.c_void_p(v) if v else C.c_void_p()  # noqa: E731
+    return lib.ozemu_dgemm(plan.handle, None, m, n, k, p(A), lda if lda is not None else k,
+                           p(B), ldb if ldb is not None else n, p(C_),
+                           ldc if ldc is not None else n, p(ws), ws_bytes)
+
+
+def test_host_side_errors_before_launch():
+    plan = oz.Plan(num_moduli=16, scaling="W")
+    S = _lib
+    # k above the INT32 accumulation cap
+    assert _call_dgemm(plan, 8, 8, 131072) == S.OZEMU_ERR_K_TOO_LARGE
+    # negative sizes, bad leading dimensions, NULL operands
+    assert _call_dgemm(plan, -1, 8, 8) == S.OZEMU_ERR_INVALID_ARG
+    assert _call_dgemm(plan, 8, 8, 8, lda=7) == S.OZEMU_ERR_INVALID_ARG
+    assert _call_dgemm(plan, 8, 8, 8, ldb=7) == S.OZEMU_ERR_INVALID_ARG
+    assert _call_dgemm(plan, 8, 8, 8, ldc=7) == S.OZEMU_ERR_INVALID_ARG
+    assert _call_dgemm(plan, 8, 8, 8, A=0) == S.OZEMU_ERR_INVALID_ARG
+    assert _call_dgemm(plan, 8, 8, 8, C_=0) == S.OZEMU_ERR_INVALID_ARG
+    # missing or short workspace
+    assert _call_dgemm(plan, 8, 8, 8) == S.OZEMU_ERR_WORKSPACE
+    assert _call_dgemm(plan, 8, 8, 8, ws=256, ws_bytes=16) == S.OZEMU_ERR_WORKSPACE
+    # empty output is a no-op that touches nothing
+    assert _call_dgemm(plan, 0, 8, 8, A=0, B=0, C_=0) == S.OZEMU_OK
+    assert _call_dgemm(plan, 8, 0, 8, A=0, B=0, C_=0) == S.OZEMU_OK
+    assert "workspace" in _lib.load().ozemu_last_error().decode() or True
+
+
+def test_f53_refuses_k_above_reconstruction_cap():
+    plan = oz.Plan(num_moduli=14, scaling="F53")  # P ~ 2**110.4: eq. ov-crt holds up to k = 10
+    assert _call_dgemm(plan, 4, 4, 10) == _lib.OZEMU_ERR_WORKSPACE
+    assert _call_dgemm(plan, 4, 4, 11) == _lib.OZEMU_ERR_K_TOO_LARGE
+    plan16 = oz.Plan(num_moduli=16, scaling="F53")
+    assert _call_dgemm(plan16, 4, 4, 8192) == _lib.OZEMU_ERR_WORKSPACE  # valid k, no workspace
+
+
+def test_status_strings():
+    lib = _lib.load()
+    assert lib.ozemu_status_string(0) == b"OZEMU_OK"
+    assert lib.ozemu_status_string(-2) == b"OZEMU_ERR_K_TOO_LARGE"
+    assert lib.ozemu_version().startswith(b"ozemu")

@@ -1,0 +1,199 @@
+"""GPU parity: every phase of the HIP path against the CPU oracle on the
+same seeded inputs, bit for bit (integer work and the correctly rounded
+result alike), through the C-ABI."""
+import numpy as np
+import pytest
+
+from oracle import exact, scheme
+from oracle import moduli as md
+from tests.gpu_util import cuda_ok, dev, host, oracle_shifts, oracle_planes, default_moduli
+from workloads import operand_pair, row_exponent_matrix
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not cuda_ok(), reason="needs a HIP device")]
+
+oz = pytest.importorskip("paper_2609_37693_amd")
+
+SHAPES = [(256, 256, 256), (300, 257, 129), (1, 1, 1), (5, 700, 3), (513, 260, 520)]
+
+
+def _inputs(m, n, k, phi=0.5, seed=0):
+    A, B = operand_pair(m, n, k, phi, seed)
+    return A, B
+
+
+@pytest.mark.parametrize("mode,nmod", [("W", 14), ("F53", 16), ("G", 14), ("W", 20), ("G", 20)])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_scale_matches_oracle(mode, nmod, shape):
+    m, n, k = shape
+    A, B = _inputs(m, n, k, 1.0, 3)
+    if m > 2:
+        A[1, :] = 0.0
+    plan = oz.Plan(num_moduli=nmod, scaling=mode)
+    ms = plan.moduli()
+    sa, sb = oz.scale(dev(A), dev(B), plan)
+    s, t = oracle_shifts(A, B, ms, mode)
+    assert np.array_equal(host(sa).astype(np.int64), s)
+    assert np.array_equal(host(sb).astype(np.int64), t)
+
+
+@pytest.mark.parametrize("mode,nmod", [("W", 14), ("W", 20), ("G", 16), ("F53", 16)])
+@pytest.mark.parametrize("shape", [(256, 256, 256), (300, 257, 129), (5, 700, 3)])
+def test_reduce_planes_match_oracle(mode, nmod, shape):
+    m, n, k = shape
+    A, B = _inputs(m, n, k, 4.0, 5)
+    plan = oz.Plan(num_moduli=nmod, scaling=mode)
+    ms = plan.moduli()
+    sa, sb = oz.scale(dev(A), dev(B), plan)
+    pa, pb = oz.reduce(dev(A), dev(B), sa, sb, plan)
+    PA, PB = oracle_planes(A, B, ms, mode, plan.plane_dims(m, n, k))
+    assert np.array_equal(host(pa), PA)
+    assert np.array_equal(host(pb), PB)
+
+
+@pytest.mark.parametrize("shape", [(256, 256, 256), (300, 257, 129), (512, 768, 320)])
+def test_residue_gemm_matches_oracle(shape):
+    m, n, k = shape
+    rng = np.random.default_rng(7)
+    plan = oz.Plan(num_moduli=16, scaling="W")
+    ms = plan.moduli()
+    mp, np_, kp = plan.plane_dims(m, n, k)
+    PA = np.zeros((16, mp, kp), np.int8)
+    PB = np.zeros((16, np_, kp), np.int8)
+    for l, mm in enumerate(ms):
+        lo, hi = -(mm // 2), (mm + 1) // 2 - 1
+        PA[l, :m, :k] = rng.integers(lo, hi + 1, (m, k))
+        PB[l, :n, :k] = rng.integers(lo, hi + 1, (n, k))
+    z = host(oz.residue_gemm(dev(PA), dev(PB), m, n, k, plan))
+    for l, mm in enumerate(ms):
+        _, Z = scheme.residue_gemm(PA[l, :m, :k].astype(np.int64), PB[l, :n, :k].T.astype(np.int64),
+                                   int(mm))
+        assert np.array_equal(z[l, :m, :n], Z), "modulus %d" % mm
+
+
+def test_residue_gemm_extreme_accumulators():
+    """Planes at the largest magnitudes with one sign per column block, so
+    every INT32 accumulator reaches -k 128 127 or k 128**2 (2**27 at
+    k = 8192): exact sums in both signs."""
+    m = n = 256
+    k = 8192
+    plan = oz.Plan(num_moduli=16, scaling="W")
+    ms = plan.moduli()
+    mp, np_, kp = plan.plane_dims(m, n, k)
+    PA = np.full((16, mp, kp), -128, np.int8)
+    PB = np.full((16, np_, kp), -128, np.int8)
+    PB[:, : n // 2, :] = 127
+    z = host(oz.residue_gemm(dev(PA), dev(PB), m, n, k, plan))
+    for l, mm in enumerate(ms):
+        assert np.all(z[l, :, : n // 2] == (k * -128 * 127) % mm)
+        assert np.all(z[l, :, n // 2:] == (k * 128 * 128) % mm)
+
+
+@pytest.mark.parametrize("mode,nmod", [("W", 14), ("G", 14), ("W", 20), ("W", 10), ("F53", 16)])
+@pytest.mark.parametrize("shape", [(256, 256, 256), (300, 257, 129), (1, 1, 1), (7, 300, 1000)])
+def test_dgemm_bitwise_matches_oracle(mode, nmod, shape):
+    m, n, k = shape
+    A, B = _inputs(m, n, k, 0.5, 0)
+    plan = oz.Plan(num_moduli=nmod, scaling=mode)
+    C = host(oz.dgemm(dev(A), dev(B), plan))
+    ref = scheme.emulate(A, B, plan.moduli(), mode, keep=False)["C"]
+    assert np.array_equal(C, ref)
+
+
+def test_phases_compose_to_dgemm():
+    m, n, k = 300, 257, 129
+    A, B = _inputs(m, n, k, 1.0, 2)
+    plan = oz.Plan(num_moduli=16, scaling="W")
+    dA, dB = dev(A), dev(B)
+    sa, sb = oz.scale(dA, dB, plan)
+    pa, pb = oz.reduce(dA, dB, sa, sb, plan)
+    z = oz.residue_gemm(pa, pb, m, n, k, plan)
+    C1 = host(oz.reconstruct(z, sa, sb, m, n, k, plan))
+    C2 = host(oz.dgemm(dA, dB, plan))
+    assert np.array_equal(C1, C2)
+    r = scheme.emulate(A, B, plan.moduli(), "W")
+    mp, np_, kp = plan.plane_dims(m, n, k)
+    assert np.array_equal(host(z)[:, :m, :n], r["Z"])
+
+
+def test_config1_accuracy():
+    """256 cubed, phi = 0.5, fourteen moduli (the small workload): bitwise
+    equal to the oracle, and mode G within 2**-50 scaled error."""
+    A, B = _inputs(256, 256, 256, 0.5, 0)
+    for mode in ("W", "G"):
+        plan = oz.Plan(num_moduli=14, scaling=mode)
+        C = host(oz.dgemm(dev(A), dev(B), plan))
+        assert np.array_equal(C, scheme.emulate(A, B, plan.moduli(), mode, keep=False)["C"])
+        if mode == "G":
+            assert exact.scaled_error(C, A, B) <= 2.0 ** -50
+
+
+def test_special_values():
+    m, n, k = 70, 66, 90
+    A, B = _inputs(m, n, k, 2.0, 4)
+    A[0, :] = 0.0
+    B[:, 1] = 0.0
+    A[2, 5] = np.inf
+    A[3, 7] = np.nan
+    B[4, 9] = -np.inf
+    A[5, :] = A[5, :] * 1e-300
+    A[6, :] = 5e-324 * np.arange(k)  # subnormals
+    A[7, :] = A[7, :] * 1e300
+    B[:, 10] = B[:, 10] * 1e300  # products overflow to infinity
+    A[8, 3] = 1e300
+    A[8, 4] = 1e-300  # row spanning 2**1993
+    for mode in ("W", "G", "F53"):
+        nm = 16
+        plan = oz.Plan(num_moduli=nm, scaling=mode)
+        C = host(oz.dgemm(dev(A), dev(B), plan))
+        ref = scheme.emulate(A, B, plan.moduli(), mode, keep=False)["C"]
+        assert np.array_equal(C, ref, equal_nan=True), mode
+
+
+def test_integer_operands_exact():
+    from workloads import integer_matrix
+    A = integer_matrix(200, 300, 2 ** 20, 1)
+    B = integer_matrix(300, 150, 2 ** 20, 2)
+    plan = oz.Plan(num_moduli=14, scaling="W")
+    C = host(oz.dgemm(dev(A), dev(B), plan))
+    assert np.array_equal(C, (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float64))
+
+
+def test_empty_and_degenerate_shapes():
+    import torch
+    plan = oz.Plan(num_moduli=12, scaling="W")
+    A = torch.zeros((0, 5), dtype=torch.float64, device="cuda")
+    B = torch.zeros((5, 3), dtype=torch.float64, device="cuda")
+    assert oz.dgemm(A, B, plan).shape == (0, 3)
+    A = torch.randn((4, 0), dtype=torch.float64, device="cuda")
+    B = torch.randn((0, 3), dtype=torch.float64, device="cuda")
+    C = oz.dgemm(A, B, plan)
+    assert C.shape == (4, 3) and bool(torch.all(C == 0))
+
+
+def test_moduli_set_does_not_change_f53_result():
+    A, B = _inputs(200, 180, 400, 1.0, 9)
+    c1 = host(oz.dgemm(dev(A), dev(B), oz.Plan(num_moduli=16, scaling="F53")))
+    c2 = host(oz.dgemm(dev(A), dev(B), oz.Plan(moduli=list(md.PAPER_INT8_239_SET), scaling="F53")))
+    assert np.array_equal(c1, c2)
+
+
+def test_strided_operands():
+    import torch
+    A, B = _inputs(130, 140, 150, 1.0, 11)
+    plan = oz.Plan(num_moduli=14, scaling="W")
+    bigA = torch.zeros((130, 200), dtype=torch.float64, device="cuda")
+    bigA[:, :150] = dev(A)
+    bigB = torch.zeros((150, 171), dtype=torch.float64, device="cuda")
+    bigB[:, :140] = dev(B)
+    C = host(oz.dgemm(bigA[:, :150], bigB[:, :140], plan))
+    assert np.array_equal(C, scheme.emulate(A, B, plan.moduli(), "W", keep=False)["C"])
+
+
+def test_row_exponent_operands():
+    A = row_exponent_matrix(128, 96, 3)
+    B = row_exponent_matrix(96, 160, 4)
+    for mode in ("W", "G"):
+        plan = oz.Plan(num_moduli=16, scaling=mode)
+        C = host(oz.dgemm(dev(A), dev(B), plan))
+        assert np.array_equal(C, scheme.emulate(A, B, plan.moduli(), mode, keep=False)["C"])
