@@ -88,24 +88,16 @@ __global__ void keys_to_shifts_kernel(int64_t count, int32_t* io, int beta,
     io[i] = s;
 }
 
-// Bound-adaptive mode: abar = ceil(|x| 2^(6 - e)) in [0, 64], computed
-// exactly from the significand; rows (A) and transposed columns (B) are
-// written K-contiguous into zero-padded planes like the residue planes.
-__device__ __forceinline__ int8_t bound_value(uint64_t bits, int32_t key) {
-    uint64_t a = bits & 0x7FFFFFFFFFFFFFFFull;
-    if (a == 0 || a >= 0x7FF0000000000000ull || key == kKeyNonFinite || key == kKeyZero) return 0;
-    uint64_t mant;
-    int ex;
-    split_double(a, mant, ex);
-    int sh = ex + 6 - key;  // |x| 2^(6-e) = mant 2^sh < 64
-    uint64_t v;
-    if (sh >= 0)
-        v = mant << sh;
-    else if (sh <= -64)
-        v = 1;
-    else
-        v = (mant + ((1ull << (-sh)) - 1)) >> (-sh);
-    return (int8_t)v;
+// Bound-adaptive mode: abar = ceil(|x| 2^(6 - e)) in [0, 64]. The scaling
+// by a power of two is exact in FP64 unless it underflows to zero, which
+// only happens for a nonzero x whose exact scaled value lies in (0, 1),
+// whose ceiling is 1. Rows (A) and transposed columns (B) are written
+// K-contiguous into zero-padded planes like the residue planes.
+__device__ __forceinline__ int8_t bound_value(double x, int32_t key) {
+    const double a = fabs(x);
+    if (!(a > 0.0) || !isfinite(a) || key == kKeyNonFinite || key == kKeyZero) return 0;
+    const double c = ceil(ldexp(a, 6 - key));
+    return (int8_t)(c > 0.0 ? (int)c : 1);
 }
 
 __global__ void bound_planes_a_kernel(int64_t m, int64_t k, const double* A, int64_t lda,
@@ -114,7 +106,7 @@ __global__ void bound_planes_a_kernel(int64_t m, int64_t k, const double* A, int
     const int64_t h = ((int64_t)blockIdx.y * blockDim.x + threadIdx.x);
     if (h >= k_pad) return;
     int8_t v = 0;
-    if (i < m && h < k) v = bound_value(__double_as_longlong(A[i * lda + h]), key_a[i]);
+    if (i < m && h < k) v = bound_value(A[i * lda + h], key_a[i]);
     bar_a[i * k_pad + h] = v;
 }
 
@@ -129,7 +121,7 @@ __global__ __launch_bounds__(256) void bound_planes_b_kernel(int64_t k, int64_t 
     for (int r = th; r < 64; r += 4) {
         int64_t h = h0 + r, j = j0 + tj;
         int8_t v = 0;
-        if (h < k && j < n) v = bound_value(__double_as_longlong(B[h * ldb + j]), key_b[j]);
+        if (h < k && j < n) v = bound_value(B[h * ldb + j], key_b[j]);
         tile[tj][r] = v;
     }
     __syncthreads();

@@ -197,3 +197,27 @@ def test_row_exponent_operands():
         plan = oz.Plan(num_moduli=16, scaling=mode)
         C = host(oz.dgemm(dev(A), dev(B), plan))
         assert np.array_equal(C, scheme.emulate(A, B, plan.moduli(), mode, keep=False)["C"])
+
+
+def test_repeated_calls_are_bitwise_stable():
+    """Regression: every call must give the same bits. Bound-adaptive scaling
+    once varied between runs (its ceiling was computed through a 64-bit
+    integer sequence); the bound planes are now formed with an exact FP64
+    ldexp and ceiling."""
+    import torch
+    m, n, k = 513, 260, 520
+    A, B = _inputs(m, n, k, 1.0, 3)
+    A[1, :] = 0.0
+    dA, dB = dev(A), dev(B)
+    for mode, nmod in (("G", 20), ("W", 16)):
+        plan = oz.Plan(num_moduli=nmod, scaling=mode)
+        s, t = oracle_shifts(A, B, plan.moduli(), mode)
+        ref = scheme.emulate(A, B, plan.moduli(), mode, keep=False)["C"]
+        for rep in range(8):
+            ws = torch.randint(0, 256, (plan.workspace_size(m, n, k),), dtype=torch.uint8,
+                               device="cuda")
+            sa, sb = oz.scale(dA, dB, plan, workspace=ws)
+            assert np.array_equal(host(sa).astype(np.int64), s), (mode, rep)
+            assert np.array_equal(host(sb).astype(np.int64), t), (mode, rep)
+            C = host(oz.dgemm(dA, dB, plan, workspace=ws))
+            assert np.array_equal(C, ref), (mode, rep)
