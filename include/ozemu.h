@@ -98,6 +98,12 @@ ozemu_status ozemu_plan_kept_bits(ozemu_plan plan, int64_t k, int* beta_a, int* 
  * (kappa_rec only limits F53; WINDOW and BOUND adapt their bits to k). */
 ozemu_status ozemu_plan_k_max(ozemu_plan plan, int64_t* k_max);
 
+/* Residue GEMM kernel variant (all give identical bits): 0 = one LDS stage
+ * refilled through registers, K step 64; 1 = software-pipelined, K step 128
+ * with two LDS stages and double-buffered MFMA operands (default). */
+ozemu_status ozemu_plan_set_gemm_variant(ozemu_plan plan, int variant);
+ozemu_status ozemu_plan_gemm_variant(ozemu_plan plan, int* variant);
+
 /* Padded sizes of the residue planes: planes of A are [N][m_pad][k_pad],
  * planes of B [N][n_pad][k_pad] (K-contiguous), residues [N][m_pad][n_pad],
  * all int8 / uint8 with these exact strides. */

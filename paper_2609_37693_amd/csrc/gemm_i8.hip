@@ -29,7 +29,7 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 constexpr int kThreads = 256;
 constexpr int kBM = kTileM;  // rows i per tile
 constexpr int kBN = kTileN;  // columns j per tile
-constexpr int kBK = kTileK;  // K bytes per stage
+constexpr int kBK = 64;       // K bytes per stage (variant 0)
 constexpr int kRowBytes = kBK + 16;
 constexpr int kStageBytes = (kBM + kBN) * kRowBytes;
 constexpr int kWaveM = 128, kWaveN = 128;
@@ -233,23 +233,217 @@ __global__ __launch_bounds__(kThreads) void residue_gemm_kernel(ModConsts mc, in
     }
 }
 
+
+// Pipelined variant: K steps of 128 bytes, two LDS stages and one register
+// stage, so the global loads of step t+2 and the LDS stores of step t+1
+// overlap the MFMAs of step t; MFMA fragments are double-buffered inside a
+// step. The loop is peeled so the steady-state body has no branches.
+constexpr int kPBK = 128;
+constexpr int kPRow = kPBK + 16;  // 36 dwords: 16 consecutive rows hit distinct banks
+constexpr int kPStage = (kBM + kBN) * kPRow;
+constexpr int kPChunks = kPBK / 16;
+constexpr int kPLoadsA = kBM * kPChunks / kThreads;
+constexpr int kPLoadsB = kBN * kPChunks / kThreads;
+static_assert(kBM * kOutRow <= 2 * kPStage, "output staging fits");
+
+template <Epi E>
+__global__ __launch_bounds__(kThreads) void residue_gemm_pipelined(ModConsts mc, int tiles_m,
+                                                                   int tiles_n, int64_t k_pad,
+                                                                   int64_t plane_a, int64_t plane_b,
+                                                                   int64_t plane_z, int64_t n_pad,
+                                                                   const int8_t* __restrict__ RA,
+                                                                   const int8_t* __restrict__ RB,
+                                                                   uint8_t* __restrict__ Z,
+                                                                   int32_t* __restrict__ gmax_a,
+                                                                   int32_t* __restrict__ gmax_b) {
+    __shared__ __align__(16) int8_t lds[2 * kPStage];
+    int l, tm, tn;
+    tile_of(blockIdx.x, tiles_m, tiles_n, l, tm, tn);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wi = wave >> 1;
+    const int wj = wave & 1;
+    const int8_t* gA = RA + (int64_t)l * plane_a + (int64_t)tm * kBM * k_pad;
+    const int8_t* gB = RB + (int64_t)l * plane_b + (int64_t)tn * kBN * k_pad;
+
+    v4i ra[kPLoadsA], rb[kPLoadsB];
+    auto gload = [&](int64_t k0) {
+#pragma unroll
+        for (int p = 0; p < kPLoadsA; ++p) {
+            const int c = tid + p * kThreads;
+            ra[p] = *reinterpret_cast<const v4i*>(gA + (int64_t)(c / kPChunks) * k_pad + k0 +
+                                                  (c % kPChunks) * 16);
+        }
+#pragma unroll
+        for (int p = 0; p < kPLoadsB; ++p) {
+            const int c = tid + p * kThreads;
+            rb[p] = *reinterpret_cast<const v4i*>(gB + (int64_t)(c / kPChunks) * k_pad + k0 +
+                                                  (c % kPChunks) * 16);
+        }
+    };
+    auto sstore = [&](int buf) {
+        int8_t* sA = lds + buf * kPStage;
+        int8_t* sB = sA + kBM * kPRow;
+#pragma unroll
+        for (int p = 0; p < kPLoadsA; ++p) {
+            const int c = tid + p * kThreads;
+            *reinterpret_cast<v4i*>(sA + (c / kPChunks) * kPRow + (c % kPChunks) * 16) = ra[p];
+        }
+#pragma unroll
+        for (int p = 0; p < kPLoadsB; ++p) {
+            const int c = tid + p * kThreads;
+            *reinterpret_cast<v4i*>(sB + (c / kPChunks) * kPRow + (c % kPChunks) * 16) = rb[p];
+        }
+    };
+
+    v16i acc[kFM][kFN];
+#pragma unroll
+    for (int a = 0; a < kFM; ++a)
+#pragma unroll
+        for (int b = 0; b < kFN; ++b) acc[a][b] = (v16i){0};
+
+    const int frag_row = lane & 31;
+    const int frag_k = (lane >> 5) * 16;
+    const int offB = (wj * kWaveN + frag_row) * kPRow + frag_k;
+    const int offA = (wi * kWaveM + frag_row) * kPRow + frag_k;
+
+    // One K step from LDS stage `cur`; optionally stores the register stage
+    // into the other LDS stage and refills the registers from global memory.
+    auto step = [&](int cur, bool store_next, bool load_next2, int64_t k_next2) {
+        const int8_t* sA = lds + cur * kPStage;
+        const int8_t* sB = sA + kBM * kPRow;
+        v4i xa[2][kFN], yb[2][kFM];
+#pragma unroll
+        for (int b = 0; b < kFN; ++b)
+            xa[0][b] = *reinterpret_cast<const v4i*>(sB + offB + b * 32 * kPRow);
+#pragma unroll
+        for (int a = 0; a < kFM; ++a)
+            yb[0][a] = *reinterpret_cast<const v4i*>(sA + offA + a * 32 * kPRow);
+#pragma unroll
+        for (int kk = 0; kk < kPBK / 32; ++kk) {
+            const int f = kk & 1;
+            if (kk + 1 < kPBK / 32) {
+#pragma unroll
+                for (int b = 0; b < kFN; ++b)
+                    xa[f ^ 1][b] = *reinterpret_cast<const v4i*>(sB + offB + b * 32 * kPRow +
+                                                                 (kk + 1) * 32);
+#pragma unroll
+                for (int a = 0; a < kFM; ++a)
+                    yb[f ^ 1][a] = *reinterpret_cast<const v4i*>(sA + offA + a * 32 * kPRow +
+                                                                 (kk + 1) * 32);
+            }
+            if (kk == 1 && store_next) sstore(cur ^ 1);
+            if (kk == 2 && load_next2) gload(k_next2);
+#pragma unroll
+            for (int a = 0; a < kFM; ++a)
+#pragma unroll
+                for (int b = 0; b < kFN; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[f][b], yb[f][a], acc[a][b],
+                                                                      0, 0, 0);
+        }
+        __syncthreads();
+    };
+
+    const int nk = (int)(k_pad / kPBK);
+    gload(0);
+    sstore(0);
+    if (nk > 1) gload(kPBK);
+    __syncthreads();
+    int kt = 0;
+    for (; kt + 2 < nk; ++kt) step(kt & 1, true, true, (int64_t)(kt + 2) * kPBK);
+    if (kt + 1 < nk) {
+        step(kt & 1, true, false, 0);
+        ++kt;
+    }
+    step(kt & 1, false, false, 0);
+
+    const int li = lane & 31;
+    const int lj = (lane >> 5) * 4;
+    if constexpr (E == Epi::kMod) {
+        const uint32_t m = mc.m[l], mu = mc.mu[l];
+        uint8_t* sO = reinterpret_cast<uint8_t*>(lds);
+#pragma unroll
+        for (int a = 0; a < kFM; ++a) {
+#pragma unroll
+            for (int b = 0; b < kFN; ++b) {
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    uint32_t packed = 0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int32_t w = acc[a][b][4 * g + q];
+                        const uint32_t aw = (uint32_t)(w < 0 ? -w : w);
+                        uint32_t r = barrett32(aw, m, mu);
+                        if (w < 0 && r != 0) r = m - r;
+                        packed |= r << (8 * q);
+                    }
+                    const int i = wi * kWaveM + a * 32 + li;
+                    const int j = wj * kWaveN + b * 32 + 8 * g + lj;
+                    *reinterpret_cast<uint32_t*>(sO + i * kOutRow + j) = packed;
+                }
+            }
+        }
+        __syncthreads();
+        uint8_t* gZ = Z + (int64_t)l * plane_z + (int64_t)tm * kBM * n_pad + (int64_t)tn * kBN;
+#pragma unroll 4
+        for (int c = tid; c < kBM * (kBN / 8); c += kThreads) {
+            const int row = c / (kBN / 8), col = (c % (kBN / 8)) * 8;
+            const uint2 v = *reinterpret_cast<const uint2*>(sO + row * kOutRow + col);
+            *reinterpret_cast<uint2*>(gZ + (int64_t)row * n_pad + col) = v;
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < kFM; ++a) {
+            int32_t rmax = 0;
+#pragma unroll
+            for (int b = 0; b < kFN; ++b)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) rmax = max(rmax, acc[a][b][q]);
+            rmax = max(rmax, __shfl_xor(rmax, 32, 64));
+            if (lane < 32) atomicMax(gmax_a + (int64_t)tm * kBM + wi * kWaveM + a * 32 + li, rmax);
+        }
+#pragma unroll
+        for (int b = 0; b < kFN; ++b) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                int32_t cmax = 0;
+#pragma unroll
+                for (int a = 0; a < kFM; ++a) cmax = max(cmax, acc[a][b][q]);
+#pragma unroll
+                for (int off = 16; off > 0; off >>= 1) cmax = max(cmax, __shfl_xor(cmax, off, 64));
+                if (li == 0) {
+                    const int j = wj * kWaveN + b * 32 + 8 * (q / 4) + lj + (q % 4);
+                    atomicMax(gmax_b + (int64_t)tn * kBN + j, cmax);
+                }
+            }
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_residue_gemm(hipStream_t st, const ModConsts& mc, int64_t m_pad, int64_t n_pad,
                                int64_t k_pad, const int8_t* planes_a, const int8_t* planes_b,
-                               uint8_t* residues) {
+                               uint8_t* residues, int variant) {
     if (m_pad <= 0 || n_pad <= 0) return hipSuccess;
     const int tiles_m = (int)(m_pad / kBM), tiles_n = (int)(n_pad / kBN);
     const int64_t blocks = (int64_t)tiles_m * tiles_n * mc.n;
-    residue_gemm_kernel<Epi::kMod><<<dim3((unsigned)blocks), dim3(kThreads), 0, st>>>(
-        mc, tiles_m, tiles_n, k_pad, m_pad * k_pad, n_pad * k_pad, m_pad * n_pad, n_pad, planes_a,
-        planes_b, residues, nullptr, nullptr);
+    if (variant == 1) {
+        residue_gemm_pipelined<Epi::kMod><<<dim3((unsigned)blocks), dim3(kThreads), 0, st>>>(
+            mc, tiles_m, tiles_n, k_pad, m_pad * k_pad, n_pad * k_pad, m_pad * n_pad, n_pad,
+            planes_a, planes_b, residues, nullptr, nullptr);
+    } else {
+        residue_gemm_kernel<Epi::kMod><<<dim3((unsigned)blocks), dim3(kThreads), 0, st>>>(
+            mc, tiles_m, tiles_n, k_pad, m_pad * k_pad, n_pad * k_pad, m_pad * n_pad, n_pad,
+            planes_a, planes_b, residues, nullptr, nullptr);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_bound_gemm(hipStream_t st, int64_t m_pad, int64_t n_pad, int64_t k_pad,
                              const int8_t* bar_a, const int8_t* bar_b, int32_t* gmax_a,
-                             int32_t* gmax_b) {
+                             int32_t* gmax_b, int variant) {
     if (m_pad <= 0 || n_pad <= 0) return hipSuccess;
     hipError_t e = launch_fill_i32(st, m_pad, 0, gmax_a);
     if (e == hipSuccess) e = launch_fill_i32(st, n_pad, 0, gmax_b);
@@ -258,8 +452,12 @@ hipError_t launch_bound_gemm(hipStream_t st, int64_t m_pad, int64_t n_pad, int64
     one.n = 1;
     const int tiles_m = (int)(m_pad / kBM), tiles_n = (int)(n_pad / kBN);
     const int64_t blocks = (int64_t)tiles_m * tiles_n;
-    residue_gemm_kernel<Epi::kMax><<<dim3((unsigned)blocks), dim3(kThreads), 0, st>>>(
-        one, tiles_m, tiles_n, k_pad, 0, 0, 0, n_pad, bar_a, bar_b, nullptr, gmax_a, gmax_b);
+    if (variant == 1)
+        residue_gemm_pipelined<Epi::kMax><<<dim3((unsigned)blocks), dim3(kThreads), 0, st>>>(
+            one, tiles_m, tiles_n, k_pad, 0, 0, 0, n_pad, bar_a, bar_b, nullptr, gmax_a, gmax_b);
+    else
+        residue_gemm_kernel<Epi::kMax><<<dim3((unsigned)blocks), dim3(kThreads), 0, st>>>(
+            one, tiles_m, tiles_n, k_pad, 0, 0, 0, n_pad, bar_a, bar_b, nullptr, gmax_a, gmax_b);
     return hipGetLastError();
 }
 

@@ -16,7 +16,7 @@ constexpr int kBetaCap = 127;   // largest kept-bit count of any mode
 // needs no bounds checks; padding entries are zero.
 constexpr int kTileM = 256;
 constexpr int kTileN = 256;
-constexpr int kTileK = 64;
+constexpr int kTileK = 128;  // a multiple of every variant's K step
 
 // Row/column key for the exponent scan: frexp exponent of the largest
 // magnitude, or these sentinels.
@@ -151,12 +151,15 @@ hipError_t launch_encode_a(hipStream_t st, const ModConsts& mc, int64_t m, int64
 hipError_t launch_encode_b(hipStream_t st, const ModConsts& mc, int64_t k, int64_t n,
                            const double* B, int64_t ldb, const int32_t* shift_b, int64_t n_pad,
                            int64_t k_pad, int8_t* planes_b);
+// GEMM kernel variants: 0 = single-stage register prefetch, K step 64;
+// 1 = pipelined, K step 128 (two LDS stages plus a register stage).
+constexpr int kGemmVariants = 2;
 hipError_t launch_residue_gemm(hipStream_t st, const ModConsts& mc, int64_t m_pad, int64_t n_pad,
                                int64_t k_pad, const int8_t* planes_a, const int8_t* planes_b,
-                               uint8_t* residues);
+                               uint8_t* residues, int variant);
 hipError_t launch_bound_gemm(hipStream_t st, int64_t m_pad, int64_t n_pad, int64_t k_pad,
                              const int8_t* bar_a, const int8_t* bar_b, int32_t* gmax_a,
-                             int32_t* gmax_b);
+                             int32_t* gmax_b, int variant);
 hipError_t launch_bound_planes_a(hipStream_t st, int64_t m, int64_t k, const double* A,
                                  int64_t lda, const int32_t* key_a, int64_t m_pad, int64_t k_pad,
                                  int8_t* bar_a);

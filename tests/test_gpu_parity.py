@@ -51,11 +51,13 @@ def test_reduce_planes_match_oracle(mode, nmod, shape):
     assert np.array_equal(host(pb), PB)
 
 
-@pytest.mark.parametrize("shape", [(256, 256, 256), (300, 257, 129), (512, 768, 320)])
-def test_residue_gemm_matches_oracle(shape):
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("shape", [(256, 256, 256), (300, 257, 129), (512, 768, 320),
+                                   (513, 260, 1100)])
+def test_residue_gemm_matches_oracle(shape, variant):
     m, n, k = shape
     rng = np.random.default_rng(7)
-    plan = oz.Plan(num_moduli=16, scaling="W")
+    plan = oz.Plan(num_moduli=16, scaling="W", gemm_variant=variant)
     ms = plan.moduli()
     mp, np_, kp = plan.plane_dims(m, n, k)
     PA = np.zeros((16, mp, kp), np.int8)
@@ -71,13 +73,14 @@ def test_residue_gemm_matches_oracle(shape):
         assert np.array_equal(z[l, :m, :n], Z), "modulus %d" % mm
 
 
-def test_residue_gemm_extreme_accumulators():
+@pytest.mark.parametrize("variant", [0, 1])
+def test_residue_gemm_extreme_accumulators(variant):
     """Planes at the largest magnitudes with one sign per column block, so
     every INT32 accumulator reaches -k 128 127 or k 128**2 (2**27 at
     k = 8192): exact sums in both signs."""
     m = n = 256
     k = 8192
-    plan = oz.Plan(num_moduli=16, scaling="W")
+    plan = oz.Plan(num_moduli=16, scaling="W", gemm_variant=variant)
     ms = plan.moduli()
     mp, np_, kp = plan.plane_dims(m, n, k)
     PA = np.full((16, mp, kp), -128, np.int8)
@@ -89,12 +92,13 @@ def test_residue_gemm_extreme_accumulators():
         assert np.all(z[l, :, n // 2:] == (k * 128 * 128) % mm)
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("mode,nmod", [("W", 14), ("G", 14), ("W", 20), ("W", 10), ("F53", 16)])
 @pytest.mark.parametrize("shape", [(256, 256, 256), (300, 257, 129), (1, 1, 1), (7, 300, 1000)])
-def test_dgemm_bitwise_matches_oracle(mode, nmod, shape):
+def test_dgemm_bitwise_matches_oracle(mode, nmod, shape, variant):
     m, n, k = shape
     A, B = _inputs(m, n, k, 0.5, 0)
-    plan = oz.Plan(num_moduli=nmod, scaling=mode)
+    plan = oz.Plan(num_moduli=nmod, scaling=mode, gemm_variant=variant)
     C = host(oz.dgemm(dev(A), dev(B), plan))
     ref = scheme.emulate(A, B, plan.moduli(), mode, keep=False)["C"]
     assert np.array_equal(C, ref)
