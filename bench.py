@@ -42,8 +42,6 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=32,
                     help="rows of C in the CPU oracle's bounded sample")
     ap.add_argument("--no-native", action="store_true")
-    ap.add_argument("--gemm-variant", type=int, default=None,
-                    help="residue GEMM kernel variant (default: the plan's)")
     return ap.parse_args()
 
 
@@ -103,7 +101,7 @@ def main():
     A_h, B_h = operand_pair(n, n, n, args.phi, args.seed)
     A = torch.from_numpy(A_h).cuda()
     B = torch.from_numpy(B_h).cuda()
-    plan = oz.Plan(num_moduli=args.moduli, scaling=args.scaling, gemm_variant=args.gemm_variant)
+    plan = oz.Plan(num_moduli=args.moduli, scaling=args.scaling)
     moduli = plan.moduli()
     C = torch.empty((n, n), dtype=torch.float64, device="cuda")
     ws = torch.empty(plan.workspace_size(n, n, n), dtype=torch.uint8, device="cuda")
@@ -141,13 +139,7 @@ def main():
                                              C_.c_void_p(pa.data_ptr()),
                                              C_.c_void_p(pb.data_ptr()),
                                              C_.c_void_p(z.data_ptr())))
-    chosen = plan.gemm_variant
-    variants_ms = {}
-    for v in range(2):
-        plan.gemm_variant = v
-        variants_ms[v] = time_stream(gemm_only, max(5, args.steps // 2), 2)
-    plan.gemm_variant = chosen
-    gemm_ms = variants_ms[chosen]
+    gemm_ms = time_stream(gemm_only, max(5, args.steps // 2), 2)
     ops = 2.0 * len(moduli) * n * n * n
     achieved = ops / (gemm_ms * 1e-3) / 1e12
 
@@ -190,8 +182,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS,
                      "unit": "TFLOP/s", "frac": achieved / INT8_PEAK_TOPS, "traffic": None,
                      "kernel": "residue_gemm_kernel (INT8 MFMA, all moduli, one launch)",
-                     "kernel_ms": gemm_ms, "gemm_variant": chosen,
-                     "variants_ms": {str(v): t for v, t in variants_ms.items()}},
+                     "kernel_ms": gemm_ms},
         "phases_ms": phases,
         "native_fp64": {"ms": native_ms,
                         "value": (flops / (native_ms * 1e-3) / 1e12) if native_ms else None,

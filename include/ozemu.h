@@ -98,15 +98,15 @@ ozemu_status ozemu_plan_kept_bits(ozemu_plan plan, int64_t k, int* beta_a, int* 
  * (kappa_rec only limits F53; WINDOW and BOUND adapt their bits to k). */
 ozemu_status ozemu_plan_k_max(ozemu_plan plan, int64_t* k_max);
 
-/* Residue GEMM kernel variant (all give identical bits): 0 = one LDS stage
- * refilled through registers, K step 64; 1 = software-pipelined, K step 128
- * with two LDS stages and double-buffered MFMA operands (default). */
-ozemu_status ozemu_plan_set_gemm_variant(ozemu_plan plan, int variant);
-ozemu_status ozemu_plan_gemm_variant(ozemu_plan plan, int* variant);
-
-/* Padded sizes of the residue planes: planes of A are [N][m_pad][k_pad],
- * planes of B [N][n_pad][k_pad] (K-contiguous), residues [N][m_pad][n_pad],
- * all int8 / uint8 with these exact strides. */
+/* Padded sizes of the residue planes. Plane l of A holds m_pad x k_pad int8
+ * (rows i of A'), plane l of B n_pad x k_pad (columns j of B'), each plane
+ * m_pad * k_pad (n_pad * k_pad) bytes, planes back to back. Inside a plane
+ * the bytes are in GEMM block order: entry (row, h) is at byte
+ *   ((row / 256) * (k_pad / 64) + h / 64) * 16384 + (row % 256) * 64
+ *   + ((((h % 64) / 16) ^ (((row % 256) / 4) % 4)) * 16) + h % 16,
+ * i.e. blocks of 256 rows x 64 K-bytes, each contiguous, with the four
+ * 16-byte chunks of a row permuted by an XOR. Residues are [N][m_pad][n_pad]
+ * uint8, row-major. m_pad and n_pad are multiples of 256, k_pad of 64. */
 ozemu_status ozemu_plane_dims(ozemu_plan plan, int64_t m, int64_t n, int64_t k,
                               int64_t* m_pad, int64_t* n_pad, int64_t* k_pad);
 
@@ -133,17 +133,17 @@ ozemu_status ozemu_scale(ozemu_plan plan, void* stream, int64_t m, int64_t n, in
                          const double* A, int64_t lda, const double* B, int64_t ldb,
                          int32_t* shift_a, int32_t* shift_b, void* workspace, size_t ws_bytes);
 
-/* Reduce (phase 2): planes_a[l][i][h] = balanced residue of A'_ih modulo
- * m_l in [-floor(m/2), ceil(m/2) - 1] as int8 (two's complement);
- * planes_b[l][j][h] likewise for B'_hj (transposed, K-contiguous). Padding
- * rows and columns are written as 0. */
+/* Reduce (phase 2): plane l of A gets, at entry (i, h), the balanced residue
+ * of A'_ih modulo m_l in [-floor(m/2), ceil(m/2) - 1] as int8 (two's
+ * complement); plane l of B gets B'_hj at entry (j, h) (a transpose). Layout
+ * as in ozemu_plane_dims; padding entries are written as 0. */
 ozemu_status ozemu_reduce(ozemu_plan plan, void* stream, int64_t m, int64_t n, int64_t k,
                           const double* A, int64_t lda, const double* B, int64_t ldb,
                           const int32_t* shift_a, const int32_t* shift_b,
                           int8_t* planes_a, int8_t* planes_b);
 
 /* GEMMs and epilogue (phases 3-4): residues[l][i][j] = (sum_h
- * planes_a[l][i][h] planes_b[l][j][h]) mod m_l in [0, m_l), INT32 sums. */
+ * A-plane_l(i, h) B-plane_l(j, h)) mod m_l in [0, m_l), exact INT32 sums. */
 ozemu_status ozemu_residue_gemm(ozemu_plan plan, void* stream, int64_t m, int64_t n, int64_t k,
                                 const int8_t* planes_a, const int8_t* planes_b,
                                 uint8_t* residues);

@@ -26,7 +26,7 @@ def version() -> str:
 class Plan:
     """An emulation plan: modulus set, scaling mode, CRT constants (host)."""
 
-    def __init__(self, num_moduli: int = 16, scaling: str = "W", moduli=None, gemm_variant=None):
+    def __init__(self, num_moduli: int = 16, scaling: str = "W", moduli=None):
         lib = _lib.load()
         self._h = C.c_void_p()
         self.scaling = scaling
@@ -39,18 +39,6 @@ class Plan:
             _lib.check(lib.ozemu_plan_create(C.byref(self._h), _lib.OZEMU_INT8,
                                              int(num_moduli), mode))
         self._lib = lib
-        if gemm_variant is not None:
-            self.gemm_variant = gemm_variant
-
-    @property
-    def gemm_variant(self) -> int:
-        v = C.c_int()
-        _lib.check(self._lib.ozemu_plan_gemm_variant(self._h, C.byref(v)))
-        return v.value
-
-    @gemm_variant.setter
-    def gemm_variant(self, variant: int):
-        _lib.check(self._lib.ozemu_plan_set_gemm_variant(self._h, int(variant)))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -173,7 +161,8 @@ def scale(A, B, plan: Plan, workspace=None):
 
 
 def reduce(A, B, shift_a, shift_b, plan: Plan):
-    """(planes_a [N, m_pad, k_pad], planes_b [N, n_pad, k_pad]) int8 tensors."""
+    """(planes_a [N, m_pad, k_pad], planes_b [N, n_pad, k_pad]) int8 tensors,
+    each plane's bytes in the GEMM block order of include/ozemu.h."""
     torch = _torch()
     A, lda = _matrix(A, "A")
     B, ldb = _matrix(B, "B")

@@ -32,8 +32,6 @@ SIGNATURES = {
     "ozemu_plan_create_moduli": (_st, [C.POINTER(_vp), C.c_int, C.c_int,
                                        C.POINTER(C.c_int32), C.c_int]),
     "ozemu_plan_destroy": (_st, [_vp]),
-    "ozemu_plan_set_gemm_variant": (_st, [_vp, C.c_int]),
-    "ozemu_plan_gemm_variant": (_st, [_vp, C.POINTER(C.c_int)]),
     "ozemu_plan_moduli": (_st, [_vp, C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_int)]),
     "ozemu_plan_kept_bits": (_st, [_vp, _i64, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "ozemu_plan_k_max": (_st, [_vp, C.POINTER(_i64)]),

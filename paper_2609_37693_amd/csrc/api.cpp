@@ -171,8 +171,7 @@ ozemu_status run_scale(const ozemu::Plan& p, hipStream_t st, int64_t m, int64_t 
         s = hip_check(launch_bound_planes_b(st, k, n, B, ldb, key_b, d.n_pad, d.k_pad, bar_b),
                       "bound_planes_b");
     if (!s)
-        s = hip_check(launch_bound_gemm(st, d.m_pad, d.n_pad, d.k_pad, bar_a, bar_b, gmax_a, gmax_b,
-                                        p.gemm_variant),
+        s = hip_check(launch_bound_gemm(st, d.m_pad, d.n_pad, d.k_pad, bar_a, bar_b, gmax_a, gmax_b),
                       "bound_gemm");
     const int L2 = half_window_bits(p);
     if (!s) s = hip_check(launch_bound_shifts(st, m, key_a, gmax_a, L2, sa), "bound_shifts_a");
@@ -233,21 +232,6 @@ ozemu_status ozemu_plan_create(ozemu_plan* out, int format, int num_moduli, int 
 
 ozemu_status ozemu_plan_destroy(ozemu_plan plan) {
     delete plan;
-    return ok();
-}
-
-ozemu_status ozemu_plan_set_gemm_variant(ozemu_plan plan, int variant) {
-    if (ozemu_status s = check_plan(plan)) return s;
-    if (variant < 0 || variant >= ozemu::kGemmVariants)
-        return fail(OZEMU_ERR_INVALID_ARG, "unknown GEMM kernel variant");
-    plan->p.gemm_variant = variant;
-    return ok();
-}
-
-ozemu_status ozemu_plan_gemm_variant(ozemu_plan plan, int* variant) {
-    if (ozemu_status s = check_plan(plan)) return s;
-    if (!variant) return fail(OZEMU_ERR_INVALID_ARG, "NULL output");
-    *variant = plan->p.gemm_variant;
     return ok();
 }
 
@@ -376,8 +360,7 @@ ozemu_status ozemu_residue_gemm(ozemu_plan plan, void* stream, int64_t m, int64_
                          "zero residues");
     }
     return hip_check(ozemu::launch_residue_gemm((hipStream_t)stream, p.mod, d.m_pad, d.n_pad,
-                                                d.k_pad, planes_a, planes_b, residues,
-                                                p.gemm_variant),
+                                                d.k_pad, planes_a, planes_b, residues),
                      "residue_gemm");
 }
 
@@ -428,8 +411,7 @@ ozemu_status ozemu_dgemm(ozemu_plan plan, void* stream, int64_t m, int64_t n, in
             ozemu::launch_encode_b(st, p.mod, k, n, B, ldb, sb, d.n_pad, d.k_pad, pb), "encode_b"))
         return s;
     if (ozemu_status s = hip_check(
-            ozemu::launch_residue_gemm(st, p.mod, d.m_pad, d.n_pad, d.k_pad, pa, pb, z,
-                                       p.gemm_variant),
+            ozemu::launch_residue_gemm(st, p.mod, d.m_pad, d.n_pad, d.k_pad, pa, pb, z),
             "residue_gemm"))
         return s;
     return hip_check(ozemu::launch_reconstruct(st, p.crt, m, n, d.m_pad, d.n_pad, z, sa, sb, C, ldc),

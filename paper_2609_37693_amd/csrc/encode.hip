@@ -4,9 +4,9 @@
 // complement) into the residue planes. Each FP64 entry is read once; all
 // moduli are produced from registers.
 //
-// Planes of A keep A's row-major order ([l][i][h], K-contiguous). Planes of
-// B are written transposed ([l][j][h]) so the GEMM reads both operands
-// K-contiguous; the transpose goes through LDS.
+// Planes of A hold row i of A' K-contiguously and planes of B column j of B'
+// (a transpose, done through LDS), both in the blocked GEMM order of
+// plane_offset, so the GEMM reads each K step of a tile as one block.
 #include "ozemu_internal.hpp"
 
 namespace ozemu {
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kEncThreads) void encode_a_kernel(ModConsts mc, int
         }
     }
     const int64_t plane_stride = m_pad * k_pad;
-    int8_t* out = planes + i * k_pad + h;
+    int8_t* out = planes + plane_offset(i, h, k_pad);
     for (int l = 0; l < mc.n; ++l) {
         const uint32_t mm = mc.m[l], mu = mc.mu[l], c32 = mc.c32[l], c16 = mc.c16[l];
         int8_t r[kEncVec];
@@ -130,8 +130,8 @@ __global__ __launch_bounds__(kEncThreads) void encode_b_kernel(ModConsts mc, int
         *reinterpret_cast<uint4*>(tile + tj * kLdsRow + hq * kEncVec) = w;
         __syncthreads();
         uint4 o = *reinterpret_cast<const uint4*>(tile + orow * kLdsRow + ochunk * kEncVec);
-        *reinterpret_cast<uint4*>(planes + (int64_t)l * plane_stride + (j0 + orow) * k_pad + h0 +
-                                  ochunk * kEncVec) = o;
+        *reinterpret_cast<uint4*>(planes + (int64_t)l * plane_stride +
+                                  plane_offset(j0 + orow, h0 + ochunk * kEncVec, k_pad)) = o;
     }
 }
 

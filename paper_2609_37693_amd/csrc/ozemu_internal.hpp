@@ -16,7 +16,21 @@ constexpr int kBetaCap = 127;   // largest kept-bit count of any mode
 // needs no bounds checks; padding entries are zero.
 constexpr int kTileM = 256;
 constexpr int kTileN = 256;
-constexpr int kTileK = 128;  // a multiple of every variant's K step
+constexpr int kTileK = 64;
+
+// Residue planes (and the bound planes) are stored in the order the GEMM
+// reads them: blocks of 256 rows x 64 K-bytes (16 KB), block (row tile tr,
+// K step ks) at byte ((tr * (k_pad / 64)) + ks) * 16384 of the plane; inside
+// a block row r takes 64 bytes and its 16-byte chunk c sits at chunk
+// position c ^ ((r >> 2) & 3). One K step of a tile is then one contiguous
+// 16 KB block, copied unchanged into LDS, where the chunk swizzle spreads
+// the MFMA operand reads of 16 consecutive rows over distinct LDS banks.
+constexpr int kPlaneRows = 256;
+constexpr int kPlaneK = 64;
+__host__ __device__ __forceinline__ int64_t plane_offset(int64_t row, int64_t h, int64_t k_pad) {
+    const int64_t tr = row >> 8, r = row & 255, ks = h >> 6, c = (h >> 4) & 3;
+    return ((tr * (k_pad >> 6) + ks) * 256 + r) * 64 + ((c ^ ((r >> 2) & 3)) << 4) + (h & 15);
+}
 
 // Row/column key for the exponent scan: frexp exponent of the largest
 // magnitude, or these sentinels.
@@ -151,15 +165,12 @@ hipError_t launch_encode_a(hipStream_t st, const ModConsts& mc, int64_t m, int64
 hipError_t launch_encode_b(hipStream_t st, const ModConsts& mc, int64_t k, int64_t n,
                            const double* B, int64_t ldb, const int32_t* shift_b, int64_t n_pad,
                            int64_t k_pad, int8_t* planes_b);
-// GEMM kernel variants: 0 = single-stage register prefetch, K step 64;
-// 1 = pipelined, K step 128 (two LDS stages plus a register stage).
-constexpr int kGemmVariants = 2;
 hipError_t launch_residue_gemm(hipStream_t st, const ModConsts& mc, int64_t m_pad, int64_t n_pad,
                                int64_t k_pad, const int8_t* planes_a, const int8_t* planes_b,
-                               uint8_t* residues, int variant);
+                               uint8_t* residues);
 hipError_t launch_bound_gemm(hipStream_t st, int64_t m_pad, int64_t n_pad, int64_t k_pad,
                              const int8_t* bar_a, const int8_t* bar_b, int32_t* gmax_a,
-                             int32_t* gmax_b, int variant);
+                             int32_t* gmax_b);
 hipError_t launch_bound_planes_a(hipStream_t st, int64_t m, int64_t k, const double* A,
                                  int64_t lda, const int32_t* key_a, int64_t m_pad, int64_t k_pad,
                                  int8_t* bar_a);

@@ -36,7 +36,6 @@ struct Plan {
     BigU P;
     int p_bits = 0;
     int64_t kappa_acc = 0;    // Lambda_INT32 / max radius^2
-    int gemm_variant = 1;     // residue GEMM kernel variant (launch_residue_gemm)
     ModConsts mod{};
     CrtConsts crt{};
 };

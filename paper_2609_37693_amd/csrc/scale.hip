@@ -91,8 +91,8 @@ __global__ void keys_to_shifts_kernel(int64_t count, int32_t* io, int beta,
 // Bound-adaptive mode: abar = ceil(|x| 2^(6 - e)) in [0, 64]. The scaling
 // by a power of two is exact in FP64 unless it underflows to zero, which
 // only happens for a nonzero x whose exact scaled value lies in (0, 1),
-// whose ceiling is 1. Rows (A) and transposed columns (B) are written
-// K-contiguous into zero-padded planes like the residue planes.
+// whose ceiling is 1. Rows (A) and transposed columns (B) are written into
+// zero-padded planes in the blocked order of the residue planes.
 __device__ __forceinline__ int8_t bound_value(double x, int32_t key) {
     const double a = fabs(x);
     if (!(a > 0.0) || !isfinite(a) || key == kKeyNonFinite || key == kKeyZero) return 0;
@@ -107,7 +107,7 @@ __global__ void bound_planes_a_kernel(int64_t m, int64_t k, const double* A, int
     if (h >= k_pad) return;
     int8_t v = 0;
     if (i < m && h < k) v = bound_value(A[i * lda + h], key_a[i]);
-    bar_a[i * k_pad + h] = v;
+    bar_a[plane_offset(i, h, k_pad)] = v;
 }
 
 // grid (ceil(n_pad/64), ceil(k_pad/64)); transpose through LDS.
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void bound_planes_b_kernel(int64_t k, int64_t 
     __syncthreads();
     for (int r = th; r < 64; r += 4) {
         int64_t j = j0 + r, h = h0 + tj;
-        if (j < n_pad && h < k_pad) bar_b[j * k_pad + h] = tile[r][tj];
+        if (j < n_pad && h < k_pad) bar_b[plane_offset(j, h, k_pad)] = tile[r][tj];
     }
 }
 

@@ -32,6 +32,33 @@ def oracle_shifts(A, B, moduli, mode):
     return s.astype(np.int64), t.astype(np.int64)
 
 
+def plane_offsets(rows: int, k_pad: int) -> np.ndarray:
+    """Byte offset of every entry (row, h) of a residue plane in the
+    library's GEMM block order (layout documented in include/ozemu.h)."""
+    r = np.arange(rows, dtype=np.int64)[:, None]
+    h = np.arange(k_pad, dtype=np.int64)[None, :]
+    rr = r % 256
+    return (((r // 256) * (k_pad // 64) + h // 64) * 16384 + rr * 64
+            + ((((h % 64) // 16) ^ ((rr // 4) % 4)) * 16) + h % 16)
+
+
+def to_blocked(P: np.ndarray) -> np.ndarray:
+    """[N, rows, k_pad] row-major planes -> the same bytes in block order."""
+    N, R, K = P.shape
+    off = plane_offsets(R, K).ravel()
+    out = np.empty((N, R * K), dtype=P.dtype)
+    for l in range(N):
+        out[l, off] = P[l].ravel()
+    return out.reshape(N, R, K)
+
+
+def from_blocked(Q: np.ndarray) -> np.ndarray:
+    """Inverse of to_blocked."""
+    N, R, K = Q.shape
+    off = plane_offsets(R, K)
+    return np.stack([Q[l].ravel()[off] for l in range(N)])
+
+
 def oracle_planes(A, B, moduli, mode, pads):
     """Zero-padded int8 residue planes [N, m_pad, k_pad], [N, n_pad, k_pad]."""
     mp, np_, kp = pads
