@@ -128,6 +128,16 @@ void kept_bits_of(const ozemu::Plan& p, int64_t k, int& ba, int& bb) {
     if (bb > ozemu::kBetaCap) bb = ozemu::kBetaCap;
 }
 
+// True when some row or column may keep more than 63 bits, so the encoder
+// needs its shift table (the bound mode's bits are decided on the device,
+// up to kBetaCap).
+bool big_encode(const ozemu::Plan& p, int64_t k) {
+    if (p.scaling == OZEMU_SCALE_BOUND) return true;
+    int ba, bb;
+    kept_bits_of(p, k, ba, bb);
+    return ba > 63 || bb > 63;
+}
+
 // Scale with all arguments validated; ws may be NULL unless BOUND.
 ozemu_status run_scale(const ozemu::Plan& p, hipStream_t st, int64_t m, int64_t n, int64_t k,
                        const double* A, int64_t lda, const double* B, int64_t ldb, int32_t* sa,
@@ -328,14 +338,16 @@ ozemu_status ozemu_reduce(ozemu_plan plan, void* stream, int64_t m, int64_t n, i
     if (d.m_pad > 0 && d.k_pad > 0) {
         if (!planes_a || !shift_a) return fail(OZEMU_ERR_INVALID_ARG, "planes_a or shift_a is NULL");
         if (ozemu_status s = hip_check(ozemu::launch_encode_a(st, p.mod, m, k, A, lda, shift_a,
-                                                              d.m_pad, d.k_pad, planes_a),
+                                                              d.m_pad, d.k_pad, planes_a,
+                                                              big_encode(p, k)),
                                        "encode_a"))
             return s;
     }
     if (d.n_pad > 0 && d.k_pad > 0) {
         if (!planes_b || !shift_b) return fail(OZEMU_ERR_INVALID_ARG, "planes_b or shift_b is NULL");
         if (ozemu_status s = hip_check(ozemu::launch_encode_b(st, p.mod, k, n, B, ldb, shift_b,
-                                                              d.n_pad, d.k_pad, planes_b),
+                                                              d.n_pad, d.k_pad, planes_b,
+                                                              big_encode(p, k)),
                                        "encode_b"))
             return s;
     }
@@ -405,10 +417,14 @@ ozemu_status ozemu_dgemm(ozemu_plan plan, void* stream, int64_t m, int64_t n, in
     Dims d = dims_of(m, n, k);
     if (ozemu_status s = run_scale(p, st, m, n, k, A, lda, B, ldb, sa, sb, ws)) return s;
     if (ozemu_status s = hip_check(
-            ozemu::launch_encode_a(st, p.mod, m, k, A, lda, sa, d.m_pad, d.k_pad, pa), "encode_a"))
+            ozemu::launch_encode_a(st, p.mod, m, k, A, lda, sa, d.m_pad, d.k_pad, pa,
+                                   big_encode(p, k)),
+            "encode_a"))
         return s;
     if (ozemu_status s = hip_check(
-            ozemu::launch_encode_b(st, p.mod, k, n, B, ldb, sb, d.n_pad, d.k_pad, pb), "encode_b"))
+            ozemu::launch_encode_b(st, p.mod, k, n, B, ldb, sb, d.n_pad, d.k_pad, pb,
+                                   big_encode(p, k)),
+            "encode_b"))
         return s;
     if (ozemu_status s = hip_check(
             ozemu::launch_residue_gemm(st, p.mod, d.m_pad, d.n_pad, d.k_pad, pa, pb, z),

@@ -14,25 +14,60 @@ namespace ozemu {
 namespace {
 
 constexpr int kEncThreads = 256;
-constexpr int kEncVec = 16;  // consecutive k entries per thread (one 16-byte store per modulus)
+constexpr int kEncVec = 16;   // consecutive k entries per thread (one 16-byte store per modulus)
+constexpr int kMaxShift = 80; // largest left shift of a significand: kBetaCap - 53 < 80
 
+// One entry, prepared once for all moduli. With kBig false the kept bits
+// are at most 63 and |A'| = mant 2^sh (or mant >> -sh) fits in 64 bits:
+// its 12-bit digits are stored. With kBig true only mant's digits are stored
+// and a positive shift is applied per modulus as a factor 2^sh mod m.
 struct Entry {
-    uint64_t mant;  // |x| = mant 2^ex
-    int sh;         // ex + shift: the truncated magnitude is mant 2^sh
+    Digits12 g;
+    int sh;    // > 0 only in the kBig form
     bool neg;
 };
 
+template <bool kBig>
 __device__ __forceinline__ Entry make_entry(double x, int32_t shift) {
     Entry e;
     uint64_t bits = (uint64_t)__double_as_longlong(x);
     uint64_t a = bits & 0x7FFFFFFFFFFFFFFFull;
     e.neg = (bits >> 63) != 0;
     if (a >= 0x7FF0000000000000ull || shift == kShiftNonFinite) a = 0;  // non-finite: zero row
+    uint64_t mant;
     int ex;
-    split_double(a, e.mant, ex);
-    e.sh = ex + shift;
-    if (e.mant == 0) e.sh = 0;
+    split_double(a, mant, ex);
+    int sh = ex + shift;
+    uint64_t v;
+    if (mant == 0) {
+        v = 0;
+        sh = 0;
+    } else if (sh <= 0) {
+        v = (sh <= -64) ? 0 : (mant >> (-sh));
+        sh = 0;
+    } else if (!kBig) {
+        v = mant << sh;  // sh <= 10: below 2^63
+        sh = 0;
+    } else {
+        v = mant;
+    }
+    e.g = digits12(v);
+    e.sh = sh;
     return e;
+}
+
+// Balanced residue (int8) of the entry modulo m_l; p2 is the LDS table of
+// 2^s mod m_l (kBig only).
+template <bool kBig>
+__device__ __forceinline__ int8_t entry_residue(const Entry& e, const ModConsts& mc, int l,
+                                                const uint8_t* p2) {
+    const uint32_t m = mc.m[l];
+    const float rcp = mc.rcp[l];
+    uint32_t r = digits_mod(e.g, mc.w12[l], m, rcp);
+    if (kBig && e.sh > 0) r = mod24(r * p2[e.sh], m, rcp);
+    if (e.neg) r = r ? m - r : 0;
+    const int32_t v = (r >= (m + 1) / 2) ? (int32_t)r - (int32_t)m : (int32_t)r;
+    return (int8_t)v;
 }
 
 __device__ __forceinline__ uint32_t pack4(const int8_t* v) {
@@ -40,13 +75,28 @@ __device__ __forceinline__ uint32_t pack4(const int8_t* v) {
            ((uint32_t)(uint8_t)v[2] << 16) | ((uint32_t)(uint8_t)v[3] << 24);
 }
 
+// Table of 2^s mod m_l for s < kMaxShift in LDS (kBig only).
+template <bool kBig>
+__device__ __forceinline__ void fill_p2(const ModConsts& mc, uint8_t* p2) {
+    if constexpr (kBig) {
+        for (int e = threadIdx.x; e < mc.n * kMaxShift; e += kEncThreads) {
+            const int l = e / kMaxShift, sft = e % kMaxShift;
+            p2[e] = (uint8_t)pow2mod(sft, mc.m[l], mc.mu[l]);
+        }
+        __syncthreads();
+    }
+}
+
 // grid: (m_pad, ceil(k_pad / (kEncThreads * kEncVec))). Thread handles
 // columns [h, h + 16) of row i.
+template <bool kBig>
 __global__ __launch_bounds__(kEncThreads) void encode_a_kernel(ModConsts mc, int64_t m, int64_t k,
                                                                const double* A, int64_t lda,
                                                                const int32_t* shift_a,
                                                                int64_t m_pad, int64_t k_pad,
                                                                int8_t* planes) {
+    __shared__ uint8_t p2[kBig ? kMaxModuli * kMaxShift : 1];
+    fill_p2<kBig>(mc, p2);
     const int64_t i = blockIdx.x;
     const int64_t h = ((int64_t)blockIdx.y * kEncThreads + threadIdx.x) * kEncVec;
     if (h >= k_pad) return;
@@ -54,28 +104,26 @@ __global__ __launch_bounds__(kEncThreads) void encode_a_kernel(ModConsts mc, int
     const int32_t s = (i < m) ? shift_a[i] : 0;
     const double* row = A + i * lda;
     if (i < m && h + kEncVec <= k && ((reinterpret_cast<uintptr_t>(row + h) & 15) == 0)) {
-        const double2* p2 = reinterpret_cast<const double2*>(row + h);
+        const double2* p2v = reinterpret_cast<const double2*>(row + h);
 #pragma unroll
         for (int q = 0; q < kEncVec / 2; ++q) {
-            double2 v = p2[q];
-            ent[2 * q] = make_entry(v.x, s);
-            ent[2 * q + 1] = make_entry(v.y, s);
+            double2 v = p2v[q];
+            ent[2 * q] = make_entry<kBig>(v.x, s);
+            ent[2 * q + 1] = make_entry<kBig>(v.y, s);
         }
     } else {
 #pragma unroll
         for (int q = 0; q < kEncVec; ++q) {
             double v = (i < m && h + q < k) ? row[h + q] : 0.0;
-            ent[q] = make_entry(v, s);
+            ent[q] = make_entry<kBig>(v, s);
         }
     }
     const int64_t plane_stride = m_pad * k_pad;
     int8_t* out = planes + plane_offset(i, h, k_pad);
     for (int l = 0; l < mc.n; ++l) {
-        const uint32_t mm = mc.m[l], mu = mc.mu[l], c32 = mc.c32[l], c16 = mc.c16[l];
         int8_t r[kEncVec];
 #pragma unroll
-        for (int q = 0; q < kEncVec; ++q)
-            r[q] = balanced_i8(trunc_residue(ent[q].mant, ent[q].sh, mm, mu, c32, c16), ent[q].neg, mm);
+        for (int q = 0; q < kEncVec; ++q) r[q] = entry_residue<kBig>(ent[q], mc, l, p2 + l * kMaxShift);
         uint4 w;
         w.x = pack4(r);
         w.y = pack4(r + 4);
@@ -93,12 +141,15 @@ __global__ __launch_bounds__(kEncThreads) void encode_a_kernel(ModConsts mc, int
 constexpr int kTB = 64;
 constexpr int kLdsRow = kTB + 16;  // bytes; padding spreads rows over banks
 
+template <bool kBig>
 __global__ __launch_bounds__(kEncThreads) void encode_b_kernel(ModConsts mc, int64_t k, int64_t n,
                                                                const double* B, int64_t ldb,
                                                                const int32_t* shift_b,
                                                                int64_t n_pad, int64_t k_pad,
                                                                int8_t* planes) {
     __shared__ __align__(16) int8_t tile[kTB * kLdsRow];
+    __shared__ uint8_t p2[kBig ? kMaxModuli * kMaxShift : 1];
+    fill_p2<kBig>(mc, p2);
     const int64_t j0 = (int64_t)blockIdx.x * kTB;
     const int64_t h0 = (int64_t)blockIdx.y * kTB;
     const int tj = threadIdx.x & 63;
@@ -110,17 +161,15 @@ __global__ __launch_bounds__(kEncThreads) void encode_b_kernel(ModConsts mc, int
     for (int q = 0; q < kEncVec; ++q) {
         const int64_t h = h0 + hq * kEncVec + q;
         double v = (j < n && h < k) ? B[h * ldb + j] : 0.0;
-        ent[q] = make_entry(v, s);
+        ent[q] = make_entry<kBig>(v, s);
     }
     const int64_t plane_stride = n_pad * k_pad;
     const int orow = threadIdx.x >> 2;    // output column of B (row of the plane)
     const int ochunk = threadIdx.x & 3;   // 16-byte chunk of K
     for (int l = 0; l < mc.n; ++l) {
-        const uint32_t mm = mc.m[l], mu = mc.mu[l], c32 = mc.c32[l], c16 = mc.c16[l];
         int8_t r[kEncVec];
 #pragma unroll
-        for (int q = 0; q < kEncVec; ++q)
-            r[q] = balanced_i8(trunc_residue(ent[q].mant, ent[q].sh, mm, mu, c32, c16), ent[q].neg, mm);
+        for (int q = 0; q < kEncVec; ++q) r[q] = entry_residue<kBig>(ent[q], mc, l, p2 + l * kMaxShift);
         uint4 w;
         w.x = pack4(r);
         w.y = pack4(r + 4);
@@ -139,22 +188,30 @@ __global__ __launch_bounds__(kEncThreads) void encode_b_kernel(ModConsts mc, int
 
 hipError_t launch_encode_a(hipStream_t st, const ModConsts& mc, int64_t m, int64_t k,
                            const double* A, int64_t lda, const int32_t* shift_a, int64_t m_pad,
-                           int64_t k_pad, int8_t* planes_a) {
+                           int64_t k_pad, int8_t* planes_a, bool big) {
     if (m_pad <= 0 || k_pad <= 0) return hipSuccess;
     const int64_t per_block = (int64_t)kEncThreads * kEncVec;
     dim3 grid((unsigned)m_pad, (unsigned)((k_pad + per_block - 1) / per_block));
-    encode_a_kernel<<<grid, dim3(kEncThreads), 0, st>>>(mc, m, k, A, lda, shift_a, m_pad, k_pad,
-                                                        planes_a);
+    if (big)
+        encode_a_kernel<true><<<grid, dim3(kEncThreads), 0, st>>>(mc, m, k, A, lda, shift_a, m_pad,
+                                                                  k_pad, planes_a);
+    else
+        encode_a_kernel<false><<<grid, dim3(kEncThreads), 0, st>>>(mc, m, k, A, lda, shift_a, m_pad,
+                                                                   k_pad, planes_a);
     return hipGetLastError();
 }
 
 hipError_t launch_encode_b(hipStream_t st, const ModConsts& mc, int64_t k, int64_t n,
                            const double* B, int64_t ldb, const int32_t* shift_b, int64_t n_pad,
-                           int64_t k_pad, int8_t* planes_b) {
+                           int64_t k_pad, int8_t* planes_b, bool big) {
     if (n_pad <= 0 || k_pad <= 0) return hipSuccess;
     dim3 grid((unsigned)(n_pad / kTB), (unsigned)(k_pad / kTB));
-    encode_b_kernel<<<grid, dim3(kEncThreads), 0, st>>>(mc, k, n, B, ldb, shift_b, n_pad, k_pad,
-                                                        planes_b);
+    if (big)
+        encode_b_kernel<true><<<grid, dim3(kEncThreads), 0, st>>>(mc, k, n, B, ldb, shift_b, n_pad,
+                                                                  k_pad, planes_b);
+    else
+        encode_b_kernel<false><<<grid, dim3(kEncThreads), 0, st>>>(mc, k, n, B, ldb, shift_b, n_pad,
+                                                                   k_pad, planes_b);
     return hipGetLastError();
 }
 

@@ -46,7 +46,57 @@ struct ModConsts {
     uint32_t mu[kMaxModuli];
     uint32_t c32[kMaxModuli];  // 2^32 mod m
     uint32_t c16[kMaxModuli];  // 2^16 mod m
+    float rcp[kMaxModuli];     // 1 / m rounded to FP32
+    uint16_t w12[kMaxModuli][6];  // 2^(12 i) mod m, i = 0..5
 };
+
+// t mod m for t < 2^24 and 2 <= m <= 256: t is exact in FP32 and t * rcp
+// is within 1/m < 1/2 of t / m, so the truncated quotient is off by at most
+// one and a single correction in either direction finishes.
+__host__ __device__ __forceinline__ uint32_t mod24(uint32_t t, uint32_t m, float rcp) {
+    const uint32_t q = (uint32_t)((float)t * rcp);
+#if defined(__HIP_DEVICE_COMPILE__)
+    int32_t r = (int32_t)t - (int32_t)__umul24(q, m);
+#else
+    int32_t r = (int32_t)t - (int32_t)(q * m);
+#endif
+    r += (r < 0) ? (int32_t)m : 0;
+    r -= (r >= (int32_t)m) ? (int32_t)m : 0;
+    return (uint32_t)r;
+}
+
+// 12-bit digits of a value below 2^72 (six digits).
+struct Digits12 {
+    uint32_t d[6];
+};
+__host__ __device__ __forceinline__ Digits12 digits12(uint64_t v) {
+    const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    Digits12 g;
+    g.d[0] = lo & 0xFFFu;
+    g.d[1] = (lo >> 12) & 0xFFFu;
+    g.d[2] = (lo >> 24) | ((hi & 0xFu) << 8);
+    g.d[3] = (hi >> 4) & 0xFFFu;
+    g.d[4] = (hi >> 16) & 0xFFFu;
+    g.d[5] = hi >> 28;
+    return g;
+}
+
+// v mod m from its digits: sum_i d_i (2^(12 i) mod m) < 6 * 2^12 * 2^8 < 2^23.
+__host__ __device__ __forceinline__ uint32_t digits_mod(const Digits12& g, const uint16_t* w,
+                                                       uint32_t m, float rcp) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint32_t t = g.d[0];
+    t = __umul24(g.d[1], w[1]) + t;
+    t = __umul24(g.d[2], w[2]) + t;
+    t = __umul24(g.d[3], w[3]) + t;
+    t = __umul24(g.d[4], w[4]) + t;
+    t = __umul24(g.d[5], w[5]) + t;
+#else
+    uint32_t t = g.d[0] + g.d[1] * w[1] + g.d[2] * w[2] + g.d[3] * w[3] + g.d[4] * w[4] +
+                 g.d[5] * w[5];
+#endif
+    return mod24(t, m, rcp);
+}
 
 // CRT constants: X = sum_l u_l M_l - q P with u_l = (z_l * inv_l) mod m_l,
 // M_l = P / m_l, inv_l = M_l^-1 mod m_l; digits little-endian, 32 bits each.
@@ -159,12 +209,14 @@ hipError_t launch_scale_cols(hipStream_t st, int64_t k, int64_t n, const double*
                              int32_t* key_b);
 hipError_t launch_keys_to_shifts(hipStream_t st, int64_t count, int32_t* key_to_shift, int beta,
                                  const int32_t* beta_per_entry);
+// Encode: `big` selects the form for kept bits above 63 (left shifts of
+// more than 10 bits), required for the bound-adaptive mode.
 hipError_t launch_encode_a(hipStream_t st, const ModConsts& mc, int64_t m, int64_t k,
                            const double* A, int64_t lda, const int32_t* shift_a, int64_t m_pad,
-                           int64_t k_pad, int8_t* planes_a);
+                           int64_t k_pad, int8_t* planes_a, bool big);
 hipError_t launch_encode_b(hipStream_t st, const ModConsts& mc, int64_t k, int64_t n,
                            const double* B, int64_t ldb, const int32_t* shift_b, int64_t n_pad,
-                           int64_t k_pad, int8_t* planes_b);
+                           int64_t k_pad, int8_t* planes_b, bool big);
 hipError_t launch_residue_gemm(hipStream_t st, const ModConsts& mc, int64_t m_pad, int64_t n_pad,
                                int64_t k_pad, const int8_t* planes_a, const int8_t* planes_b,
                                uint8_t* residues);

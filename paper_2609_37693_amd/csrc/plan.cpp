@@ -218,6 +218,12 @@ std::string build_plan(Plan& p, int format, const std::vector<int>& moduli_in, i
         p.mod.mu[l] = mu;
         p.mod.c32[l] = (uint32_t)((1ull << 32) % m);
         p.mod.c16[l] = (uint32_t)((1ull << 16) % m);
+        p.mod.rcp[l] = 1.0f / (float)m;
+        for (int i = 0; i < 6; ++i) {
+            uint64_t w = 1 % m;
+            for (int b = 0; b < 12 * i; ++b) w = (w * 2) % m;
+            p.mod.w12[l][i] = (uint16_t)w;
+        }
         p.crt.m[l] = m;
         p.crt.mu[l] = mu;
         p.crt.rcp[l] = 1.0 / (double)m;
