@@ -62,6 +62,36 @@ def time_stream(fn, iters, warmup):
     return s.elapsed_time(e) / iters
 
 
+GEMM_SOURCES = ("paper_2609_37693_amd/csrc/gemm_i8.hip",
+                "paper_2609_37693_amd/csrc/ozemu_internal.hpp")
+TRAFFIC_PROFILE = os.path.join("profiles", "residue_gemm_8192x16.md")
+
+
+def committed_traffic(n, num_moduli):
+    """HBM bytes per residue-GEMM launch measured with rocprofv3 (FETCH_SIZE
+    and WRITE_SIZE, calibrated on a streaming kernel of known size) and
+    recorded in the profile summary; None when the workload differs or the
+    kernel source changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(os.path.join(ROOT, TRAFFIC_PROFILE)).read()
+    except OSError:
+        return None
+    found = re.search(r"```json\n(\{.*?\})\n```", text, re.S)
+    if not found:
+        return None
+    rec = json.loads(found.group(1))
+    h = hashlib.sha256()
+    for f in GEMM_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest()[:16] != rec.get("source_hash"):
+        return None
+    if rec.get("n") != n or rec.get("moduli") != num_moduli:
+        return None
+    return rec.get("traffic_bytes")
+
+
 def cpu_baseline(A, B, moduli, mode, rows):
     """The CPU oracle, as it stands, on a bounded sample: rows [0, rows) of
     C at full K and N (every step of the scheme, B's scaling and residues
@@ -180,7 +210,8 @@ def main():
                    "m": n, "n": n, "k": n, "phi": args.phi, "moduli": len(moduli),
                    "scaling_mode": args.scaling, "seed": args.seed},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS,
-                     "unit": "TFLOP/s", "frac": achieved / INT8_PEAK_TOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / INT8_PEAK_TOPS,
+                     "traffic": committed_traffic(n, len(moduli)),
                      "kernel": "residue_gemm_kernel (INT8 MFMA, all moduli, one launch)",
                      "kernel_ms": gemm_ms},
         "phases_ms": phases,
