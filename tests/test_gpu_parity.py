@@ -224,3 +224,26 @@ def test_repeated_calls_are_bitwise_stable():
             assert np.array_equal(host(sb).astype(np.int64), t), (mode, rep)
             C = host(oz.dgemm(dA, dB, plan, workspace=ws))
             assert np.array_equal(C, ref), (mode, rep)
+
+
+def test_full_size_sampled_parity_and_error():
+    """The bench workload (8192 cubed, phi = 0.5, sixteen moduli, mode W):
+    C on 48 sampled rows x 48 sampled columns is bitwise equal to the oracle
+    (in mode W a row's shift depends only on that row and K), and the exact
+    scaled error max |C - AB| / (|A||B|) over the sample is at most 2**-50."""
+    import torch
+    n = 8192
+    A, B = operand_pair(n, n, n, 0.5, 0)
+    plan = oz.Plan(num_moduli=16, scaling="W")
+    C = oz.dgemm(dev(A), dev(B), plan)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1)
+    rows = np.sort(rng.choice(n, 48, replace=False))
+    cols = np.sort(rng.choice(n, 48, replace=False))
+    Cs = host(C)[np.ix_(rows, cols)]
+    As = np.ascontiguousarray(A[rows])
+    Bs = np.ascontiguousarray(B[:, cols])
+    ref = scheme.emulate(As, Bs, plan.moduli(), "W", blas=True, keep=False)["C"]
+    assert np.array_equal(Cs, ref)
+    err = exact.scaled_error(Cs, As, Bs)
+    assert err <= 2.0 ** -50, err
