@@ -155,6 +155,56 @@ ozemu_status ozemu_reconstruct(ozemu_plan plan, void* stream, int64_t m, int64_t
                                const uint8_t* residues, const int32_t* shift_a,
                                const int32_t* shift_b, double* C, int64_t ldc);
 
+/* ---- Training: a forward that keeps what its backward reuses. The paper
+ * covers one product; the two gradient products of Y = X W are emulated
+ * with the same scheme (Sec. II-A scaling, Sec. II-B residues, Sec. V-A
+ * phases), reusing the forward's truncated operands X', W' as cached
+ * residue planes. Modes F53 and WINDOW; BOUND returns UNSUPPORTED. ---- */
+
+/* Y = X W (X m x k, W k x n, Y m x n, row-major with leading dimensions),
+ * emulated as ozemu_dgemm except that the kept bits are those of
+ * ozemu_plan_kept_bits at K* = max(m, n, k), the largest inner dimension
+ * of the forward and of both backward products (so Y may carry fewer bits
+ * than ozemu_dgemm gives when m or n exceeds k). Also writes the cache:
+ *   shift_x[m]   row shifts s_i of X (as ozemu_scale's shift_a),
+ *   shift_w[n]   column shifts t_j of W,
+ *   planes_x     residue planes of X' (ozemu_reduce's planes_a layout,
+ *                N x m_pad x k_pad bytes from ozemu_plane_dims(m, n, k)),
+ *   planes_w     residue planes of W' (planes_b layout, N x n_pad x k_pad).
+ * All device buffers owned by the caller. `workspace` holds
+ * ozemu_workspace_size(m, n, k) bytes, 256-byte aligned. The caps of the
+ * plan must hold at K* (OZEMU_ERR_K_TOO_LARGE otherwise). When m, n or k
+ * is 0 the cache is not written (both gradients are then empty or zero). */
+ozemu_status ozemu_dgemm_fwd_cache(ozemu_plan plan, void* stream, int64_t m, int64_t n, int64_t k,
+                                   const double* X, int64_t ldx, const double* W, int64_t ldw,
+                                   double* Y, int64_t ldy, int32_t* shift_x, int32_t* shift_w,
+                                   int8_t* planes_x, int8_t* planes_w, void* workspace,
+                                   size_t ws_bytes);
+
+/* Bytes of device workspace ozemu_dgemm_bwd needs for forward shape (m, n, k). */
+ozemu_status ozemu_bwd_workspace_size(ozemu_plan plan, int64_t m, int64_t n, int64_t k,
+                                      size_t* bytes);
+
+/* Gradients of Y = X W from dY (m x n) and the cache of
+ * ozemu_dgemm_fwd_cache with the same plan and (m, n, k):
+ *   dX (m x k, lddx >= k) = dY W^T: dY is folded by the cached column
+ *     shifts (entry (i, j) taken as dY_ij 2^-t_j, exactly), row-scaled to
+ *     keep the bits the CRT window leaves at inner dimension n beside W's
+ *     cached bits, truncated and reduced; the cached W' planes are
+ *     transposed on the device and multiplied per modulus;
+ *     dX_ih = RN((D W'^T)_ih 2^-s''_i), one rounding.
+ *   dW (k x n, lddw >= n) = X^T dY: the same with the rows of dY folded by
+ *     the cached row shifts s_i, column scaling, and X' transposed.
+ * Either output may be NULL to skip it. A NaN or infinity in a row of dY
+ * makes that row of dX NaN (a column of dY: that column of dW); a row of X
+ * or column of W that held one in the forward makes all of dW (all of dX)
+ * NaN. `workspace`: ozemu_bwd_workspace_size bytes, 256-byte aligned. */
+ozemu_status ozemu_dgemm_bwd(ozemu_plan plan, void* stream, int64_t m, int64_t n, int64_t k,
+                             const double* dY, int64_t lddy, const int32_t* shift_x,
+                             const int32_t* shift_w, const int8_t* planes_x,
+                             const int8_t* planes_w, double* dX, int64_t lddx, double* dW,
+                             int64_t lddw, void* workspace, size_t ws_bytes);
+
 const char* ozemu_status_string(int status);
 const char* ozemu_last_error(void);
 const char* ozemu_version(void);

@@ -58,9 +58,11 @@ __all__ = ["cache_bits", "forward_cached", "backward_bits", "fold_shifts",
            "fold_truncate", "backward_dx", "backward_dw"]
 
 
-def cache_bits(mode: str, P: int, m: int, n: int, k: int):
-    """(beta_X, beta_W) of the cached forward: kept bits at K* = max(m, n, k)."""
-    kstar = max(m, n, k, 1)
+def cache_bits(mode: str, P: int, m: int, n: int, k: int, kstar=None):
+    """(beta_X, beta_W) of the cached forward: kept bits at K* = max(m, n, k)
+    (``kstar`` gives K* of a whole problem when rows or columns of it are
+    sampled)."""
+    kstar = max(m, n, k, 1) if kstar is None else kstar
     bx, bw = scheme.kept_bits(mode, P, kstar)
     if mode == "F53" and 2 * kstar * (2 ** bx - 1) * (2 ** bw - 1) >= P:
         raise ValueError("max(m, n, k) exceeds kappa_rec for this modulus set")
@@ -81,16 +83,22 @@ def backward_bits(mode: str, P: int, inner: int, cached_bits: int) -> int:
     return beta
 
 
-def forward_cached(X, W, moduli, mode: str = "W"):
+def forward_cached(X, W, moduli, mode: str = "W", kstar=None, blas: bool = False):
     """Forward with kept bits at max(m, n, k); returns the cache the
     backward needs: shifts s, t, truncated X', W', their residue planes
-    (RX[l]: m x k, RW[l]: k x n), the finite masks, the bits and Y."""
+    (RX[l]: m x k, RW[l]: k x n), the finite masks, the bits and Y.
+
+    Rows of X and columns of W are scaled independently, so a sample of
+    rows of X (columns of W) with ``kstar`` set to the whole problem's K*
+    gives exactly those rows (columns) of the whole problem's cache and Y.
+    ``blas`` forms the residue products through FP64 BLAS (exact, see
+    ``scheme.residue_gemm``)."""
     X = np.asarray(X, dtype=np.float64)
     W = np.asarray(W, dtype=np.float64)
     m, k = X.shape
     n = W.shape[1]
     P = product(moduli)
-    bx, bw = cache_bits(mode, P, m, n, k)
+    bx, bw = cache_bits(mode, P, m, n, k, kstar)
     finX = np.all(np.isfinite(X), axis=1)
     finW = np.all(np.isfinite(W), axis=0)
     X0 = np.where(finX[:, None], X, 0.0)
@@ -105,12 +113,12 @@ def forward_cached(X, W, moduli, mode: str = "W"):
     RW = [scheme.balanced_residues(Wi, int(mm)) for mm in moduli]
     Z = np.zeros((len(moduli), m, n), dtype=np.int64)
     for l, mm in enumerate(moduli):
-        _, Z[l] = scheme.residue_gemm(RX[l], RW[l], int(mm))
+        _, Z[l] = scheme.residue_gemm(RX[l], RW[l], int(mm), blas=blas)
     Y = scheme.round_scaled(scheme.crt_balanced(Z, moduli), s, t)
     Y[(~finX)[:, None] | (~finW)[None, :]] = np.nan
     return {"s": s, "t": t, "bits": (bx, bw), "Xint": Xi, "Wint": Wi, "RX": RX,
             "RW": RW, "finX": finX, "finW": finW, "Y": Y, "mode": mode,
-            "moduli": list(moduli), "shape": (m, n, k)}
+            "moduli": list(moduli), "shape": (m, n, k), "blas": blas}
 
 
 def fold_shifts(D, fold, beta: int, axis: int):
@@ -152,7 +160,9 @@ def _crt_round(Zs, moduli, s_rows, t_cols):
 def backward_dx(dY, cache, residues: bool = True):
     """dX = dY W^T through the cached W' (module header). ``residues``
     False forms D W'^T by an exact integer product instead of residues and
-    the CRT (the definition the residue path must reproduce)."""
+    the CRT (the definition the residue path must reproduce). Rows of dX
+    depend only on the same rows of dY, so a cache of sampled rows of X
+    takes the same rows of dY."""
     dY = np.asarray(dY, dtype=np.float64)
     m, n, k = cache["shape"]
     moduli = cache["moduli"]
@@ -167,7 +177,7 @@ def backward_dx(dY, cache, residues: bool = True):
         Z = np.zeros((len(moduli), m, k), dtype=np.int64)
         for l, mm in enumerate(moduli):
             rd = scheme.balanced_residues(D, int(mm))
-            _, Z[l] = scheme.residue_gemm(rd, cache["RW"][l].T, int(mm))
+            _, Z[l] = scheme.residue_gemm(rd, cache["RW"][l].T, int(mm), blas=cache["blas"])
         dX = _crt_round(Z, moduli, s2, zero)
     else:
         Xp = exact.exact_int_matmul(D, np.ascontiguousarray(cache["Wint"].T))
@@ -177,7 +187,9 @@ def backward_dx(dY, cache, residues: bool = True):
 
 
 def backward_dw(dY, cache, residues: bool = True):
-    """dW = X^T dY through the cached X' (module header)."""
+    """dW = X^T dY through the cached X' (module header). Columns of dW
+    depend only on the same columns of dY, so a cache of sampled columns
+    of W takes the same columns of dY."""
     dY = np.asarray(dY, dtype=np.float64)
     m, n, k = cache["shape"]
     moduli = cache["moduli"]
@@ -192,7 +204,8 @@ def backward_dw(dY, cache, residues: bool = True):
         Z = np.zeros((len(moduli), k, n), dtype=np.int64)
         for l, mm in enumerate(moduli):
             re = scheme.balanced_residues(E, int(mm))
-            _, Z[l] = scheme.residue_gemm(np.ascontiguousarray(cache["RX"][l].T), re, int(mm))
+            _, Z[l] = scheme.residue_gemm(np.ascontiguousarray(cache["RX"][l].T), re, int(mm),
+                                          blas=cache["blas"])
         dW = _crt_round(Z, moduli, zero, t3)
     else:
         Xp = exact.exact_int_matmul(np.ascontiguousarray(cache["Xint"].T), E)

@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import OzemuError, SCALING, SHIFT_NONFINITE
 
 __all__ = ["Plan", "dgemm", "scale", "reduce", "residue_gemm", "reconstruct", "OzemuError",
-           "SHIFT_NONFINITE", "version"]
+           "SHIFT_NONFINITE", "version", "ForwardCache", "dgemm_fwd_cache", "dgemm_bwd"]
 
 
 def version() -> str:
@@ -76,6 +76,12 @@ class Plan:
     def workspace_size(self, m: int, n: int, k: int) -> int:
         v = C.c_size_t()
         _lib.check(self._lib.ozemu_workspace_size(self._h, int(m), int(n), int(k), C.byref(v)))
+        return v.value
+
+    def bwd_workspace_size(self, m: int, n: int, k: int) -> int:
+        v = C.c_size_t()
+        _lib.check(self._lib.ozemu_bwd_workspace_size(self._h, int(m), int(n), int(k),
+                                                      C.byref(v)))
         return v.value
 
 
@@ -205,3 +211,73 @@ def reconstruct(residues, shift_a, shift_b, m: int, n: int, k: int, plan: Plan, 
                                            _ptr(residues.contiguous()), _ptr(shift_a),
                                            _ptr(shift_b), _ptr(out), ldc))
     return out
+
+
+class ForwardCache:
+    """What a cached forward keeps for its backward: the row shifts of X,
+    the column shifts of W and the residue planes of X' and W' (device
+    tensors), with the forward's shape and plan."""
+
+    def __init__(self, plan, m, n, k, shift_x, shift_w, planes_x, planes_w):
+        self.plan, self.m, self.n, self.k = plan, m, n, k
+        self.shift_x, self.shift_w = shift_x, shift_w
+        self.planes_x, self.planes_w = planes_x, planes_w
+
+    def nbytes(self) -> int:
+        return sum(t.numel() * t.element_size()
+                   for t in (self.shift_x, self.shift_w, self.planes_x, self.planes_w))
+
+
+def dgemm_fwd_cache(X, W, plan: Plan, out=None, workspace=None):
+    """(Y, cache): Y = X @ W emulated with kept bits split at max(m, n, k),
+    and the cache ``dgemm_bwd`` reuses."""
+    torch = _torch()
+    X, ldx = _matrix(X, "X")
+    W, ldw = _matrix(W, "W")
+    m, k = X.shape
+    k2, n = W.shape
+    if k != k2:
+        raise ValueError("inner dimensions differ: %d vs %d" % (k, k2))
+    if out is None:
+        out = torch.empty((m, n), dtype=torch.float64, device=X.device)
+    ldy = out.stride(0) if out.numel() > 0 else max(1, n)
+    mp, np_, kp = plan.plane_dims(m, n, k)
+    N = len(plan.moduli())
+    sx = torch.empty(max(m, 1), dtype=torch.int32, device=X.device)
+    sw = torch.empty(max(n, 1), dtype=torch.int32, device=X.device)
+    px = torch.empty((N, mp, kp), dtype=torch.int8, device=X.device)
+    pw = torch.empty((N, np_, kp), dtype=torch.int8, device=X.device)
+    nbytes = plan.workspace_size(m, n, k)
+    if workspace is None:
+        workspace = _WS.setdefault((X.device, id(plan)), _Workspace()).get(nbytes, X.device)
+    _lib.check(plan._lib.ozemu_dgemm_fwd_cache(
+        plan.handle, _stream_ptr(), m, n, k, _ptr(X), ldx, _ptr(W), ldw, _ptr(out), ldy,
+        _ptr(sx), _ptr(sw), _ptr(px), _ptr(pw), _ptr(workspace), workspace.numel()))
+    return out, ForwardCache(plan, m, n, k, sx, sw, px, pw)
+
+
+def dgemm_bwd(dY, cache: ForwardCache, need_dx: bool = True, need_dw: bool = True,
+              workspace=None):
+    """(dX, dW) of Y = X @ W from dY and the forward's cache (None for a
+    gradient not asked for): dX = dY W^T and dW = X^T dY, emulated through
+    the cached residue planes."""
+    torch = _torch()
+    dY, lddy = _matrix(dY, "dY")
+    m, n, k = cache.m, cache.n, cache.k
+    if tuple(dY.shape) != (m, n):
+        raise ValueError("dY has shape %s, the forward's output %s" % (tuple(dY.shape), (m, n)))
+    plan = cache.plan
+    dX = torch.empty((m, k), dtype=torch.float64, device=dY.device) if need_dx else None
+    dW = torch.empty((k, n), dtype=torch.float64, device=dY.device) if need_dw else None
+    nbytes = plan.bwd_workspace_size(m, n, k)
+    if workspace is None:
+        workspace = _WS.setdefault((dY.device, id(plan), "bwd"), _Workspace()).get(nbytes,
+                                                                                    dY.device)
+    lddx = max(1, k)
+    lddw = max(1, n)
+    # a requested gradient with no entries passes a non-NULL pointer of 0 size
+    _lib.check(plan._lib.ozemu_dgemm_bwd(
+        plan.handle, _stream_ptr(), m, n, k, _ptr(dY), lddy, _ptr(cache.shift_x),
+        _ptr(cache.shift_w), _ptr(cache.planes_x), _ptr(cache.planes_w),
+        _ptr(dX), lddx, _ptr(dW), lddw, _ptr(workspace), workspace.numel()))
+    return dX, dW

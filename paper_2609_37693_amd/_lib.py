@@ -46,6 +46,11 @@ SIGNATURES = {
                            _vp]),
     "ozemu_residue_gemm": (_st, [_vp, _vp, _i64, _i64, _i64, _vp, _vp, _vp]),
     "ozemu_reconstruct": (_st, [_vp, _vp, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _i64]),
+    "ozemu_dgemm_fwd_cache": (_st, [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp,
+                                    _i64, _vp, _vp, _vp, _vp, _vp, C.c_size_t]),
+    "ozemu_bwd_workspace_size": (_st, [_vp, _i64, _i64, _i64, C.POINTER(C.c_size_t)]),
+    "ozemu_dgemm_bwd": (_st, [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp,
+                              _i64, _vp, _i64, _vp, C.c_size_t]),
     "ozemu_status_string": (C.c_char_p, [C.c_int]),
     "ozemu_last_error": (C.c_char_p, []),
     "ozemu_version": (C.c_char_p, []),

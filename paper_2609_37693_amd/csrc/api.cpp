@@ -3,6 +3,7 @@
 // Reconstruct) on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -187,6 +188,57 @@ ozemu_status run_scale(const ozemu::Plan& p, hipStream_t st, int64_t m, int64_t 
     if (!s) s = hip_check(launch_bound_shifts(st, m, key_a, gmax_a, L2, sa), "bound_shifts_a");
     if (!s) s = hip_check(launch_bound_shifts(st, n, key_b, gmax_b, L2, sb), "bound_shifts_b");
     return s;
+}
+
+// Kept bits of a cached forward: split at the largest inner dimension of
+// the forward and both backward products, K* = max(m, n, k).
+int64_t cache_k(int64_t m, int64_t n, int64_t k) { return std::max(std::max(m, n), k); }
+
+// Kept bits of dY in a backward product of inner dimension `inner` against
+// cached operand bits `cached`: all the window leaves (53 in F53).
+int backward_bits(const ozemu::Plan& p, int64_t inner, int cached) {
+    if (p.scaling == OZEMU_SCALE_F53) return 53;
+    int b = ozemu::window_bits(p, inner) - cached;
+    return b > ozemu::kBetaCap ? ozemu::kBetaCap : b;
+}
+
+ozemu_status check_cache_plan(const ozemu::Plan& p, int64_t m, int64_t n, int64_t k) {
+    if (p.scaling == OZEMU_SCALE_BOUND)
+        return fail(OZEMU_ERR_UNSUPPORTED, "cached forward and backward support F53 and WINDOW");
+    if (m < 0 || n < 0 || k < 0) return fail(OZEMU_ERR_INVALID_ARG, "negative dimension");
+    if (k > (1ll << 31)) return fail(OZEMU_ERR_INVALID_ARG, "dimension too large");
+    // every product's inner dimension (k, n, m) must pass the caps at K*
+    return check_shape(p, m, n, cache_k(m, n, k));
+}
+
+// Backward workspace: the fold shifts, a zero shift vector and, shared by
+// the two products in turn, the fresh operand's planes, the transposed
+// cached planes and the residues.
+struct BwdLayout {
+    size_t shift_dx, shift_dw, zeros, planes_fresh, planes_t, residues, total;
+};
+
+BwdLayout bwd_layout_of(const ozemu::Plan& p, int64_t m, int64_t n, int64_t k) {
+    const size_t N = (size_t)p.n;
+    const size_t mp = (size_t)round_up(m, ozemu::kTileM), np = (size_t)round_up(n, ozemu::kTileN);
+    const size_t kp = (size_t)round_up(k, ozemu::kTileM);
+    BwdLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    L.shift_dx = take(sizeof(int32_t) * mp);
+    L.shift_dw = take(sizeof(int32_t) * np);
+    L.zeros = take(sizeof(int32_t) * std::max(kp, (size_t)1));
+    // dX: fresh mp x np, transposed W kp x np, residues mp x kp
+    // dW: fresh np x mp, transposed X kp x mp, residues kp x np
+    L.planes_fresh = take(N * mp * np);
+    L.planes_t = take(N * kp * std::max(mp, np));
+    L.residues = take(N * kp * std::max(mp, np));
+    L.total = off;
+    return L;
 }
 
 }  // namespace
@@ -432,6 +484,149 @@ ozemu_status ozemu_dgemm(ozemu_plan plan, void* stream, int64_t m, int64_t n, in
         return s;
     return hip_check(ozemu::launch_reconstruct(st, p.crt, m, n, d.m_pad, d.n_pad, z, sa, sb, C, ldc),
                      "reconstruct");
+}
+
+ozemu_status ozemu_dgemm_fwd_cache(ozemu_plan plan, void* stream, int64_t m, int64_t n, int64_t k,
+                                   const double* X, int64_t ldx, const double* W, int64_t ldw,
+                                   double* Y, int64_t ldy, int32_t* shift_x, int32_t* shift_w,
+                                   int8_t* planes_x, int8_t* planes_w, void* workspace,
+                                   size_t ws_bytes) {
+    if (ozemu_status s = check_plan(plan)) return s;
+    const ozemu::Plan& p = plan->p;
+    if (ozemu_status s = check_cache_plan(p, m, n, k)) return s;
+    if (m == 0 || n == 0) return ok();
+    if (ozemu_status s = check_operands(m, n, k, X, ldx, W, ldw)) return s;
+    if (!Y || ldy < n) return fail(OZEMU_ERR_INVALID_ARG, "Y is NULL or ldy < n");
+    hipStream_t st = (hipStream_t)stream;
+    if (k == 0) return hip_check(ozemu::launch_zero_c(st, m, n, Y, ldy), "zero Y");
+    if (!shift_x || !shift_w || !planes_x || !planes_w)
+        return fail(OZEMU_ERR_INVALID_ARG, "cache buffers are NULL");
+    Layout L = layout_of(p, m, n, k);
+    if (!workspace || ws_bytes < L.total)
+        return fail(OZEMU_ERR_WORKSPACE, "workspace smaller than ozemu_workspace_size");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255)
+        return fail(OZEMU_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+    uint8_t* z = reinterpret_cast<uint8_t*>(static_cast<char*>(workspace) + L.residues);
+    Dims d = dims_of(m, n, k);
+    const int64_t ks = cache_k(m, n, k);
+    int bx, bw;
+    kept_bits_of(p, ks, bx, bw);
+    const bool big = bx > 63 || bw > 63;
+    using namespace ozemu;
+    ozemu_status s = hip_check(launch_scale_rows(st, m, k, X, ldx, shift_x), "scale_rows");
+    if (!s) s = hip_check(launch_scale_cols(st, k, n, W, ldw, shift_w), "scale_cols");
+    if (!s) s = hip_check(launch_keys_to_shifts(st, m, shift_x, bx, nullptr), "shifts_x");
+    if (!s) s = hip_check(launch_keys_to_shifts(st, n, shift_w, bw, nullptr), "shifts_w");
+    if (!s)
+        s = hip_check(launch_encode_a(st, p.mod, m, k, X, ldx, shift_x, d.m_pad, d.k_pad, planes_x,
+                                      big),
+                      "encode_x");
+    if (!s)
+        s = hip_check(launch_encode_b(st, p.mod, k, n, W, ldw, shift_w, d.n_pad, d.k_pad, planes_w,
+                                      big),
+                      "encode_w");
+    if (!s)
+        s = hip_check(launch_residue_gemm(st, p.mod, d.m_pad, d.n_pad, d.k_pad, planes_x, planes_w, z),
+                      "residue_gemm");
+    if (!s)
+        s = hip_check(launch_reconstruct(st, p.crt, m, n, d.m_pad, d.n_pad, z, shift_x, shift_w, Y,
+                                         ldy),
+                      "reconstruct");
+    return s;
+}
+
+ozemu_status ozemu_bwd_workspace_size(ozemu_plan plan, int64_t m, int64_t n, int64_t k,
+                                      size_t* bytes) {
+    if (ozemu_status s = check_plan(plan)) return s;
+    if (!bytes) return fail(OZEMU_ERR_INVALID_ARG, "bytes is NULL");
+    if (m < 0 || n < 0 || k < 0) return fail(OZEMU_ERR_INVALID_ARG, "negative dimension");
+    *bytes = bwd_layout_of(plan->p, m, n, k).total;
+    return ok();
+}
+
+ozemu_status ozemu_dgemm_bwd(ozemu_plan plan, void* stream, int64_t m, int64_t n, int64_t k,
+                             const double* dY, int64_t lddy, const int32_t* shift_x,
+                             const int32_t* shift_w, const int8_t* planes_x,
+                             const int8_t* planes_w, double* dX, int64_t lddx, double* dW,
+                             int64_t lddw, void* workspace, size_t ws_bytes) {
+    if (ozemu_status s = check_plan(plan)) return s;
+    const ozemu::Plan& p = plan->p;
+    if (ozemu_status s = check_cache_plan(p, m, n, k)) return s;
+    const bool want_dx = dX && m > 0 && k > 0;
+    const bool want_dw = dW && k > 0 && n > 0;
+    if (want_dx && lddx < k) return fail(OZEMU_ERR_INVALID_ARG, "lddx < k");
+    if (want_dw && lddw < n) return fail(OZEMU_ERR_INVALID_ARG, "lddw < n");
+    hipStream_t st = (hipStream_t)stream;
+    using namespace ozemu;
+    // an empty inner dimension gives a zero gradient
+    const bool dx_zero = want_dx && n == 0, dw_zero = want_dw && m == 0;
+    const bool dx_run = want_dx && !dx_zero, dw_run = want_dw && !dw_zero;
+    if (dx_run || dw_run) {
+        if (!dY || lddy < n) return fail(OZEMU_ERR_INVALID_ARG, "dY is NULL or lddy < n");
+        if ((dx_run && (!shift_w || !planes_w)) || (dw_run && (!shift_x || !planes_x)))
+            return fail(OZEMU_ERR_INVALID_ARG, "cache buffers are NULL");
+    }
+    int bx, bw;
+    kept_bits_of(p, cache_k(m, n, k), bx, bw);
+    const int beta_dx = dx_run ? backward_bits(p, n, bw) : 1;
+    const int beta_dw = dw_run ? backward_bits(p, m, bx) : 1;
+    if (beta_dx < 1 || beta_dw < 1)
+        return fail(OZEMU_ERR_K_TOO_LARGE, "no bits left for dY at this inner dimension");
+    BwdLayout L = bwd_layout_of(p, m, n, k);
+    if (dx_run || dw_run) {
+        if (!workspace || ws_bytes < L.total)
+            return fail(OZEMU_ERR_WORKSPACE, "workspace smaller than ozemu_bwd_workspace_size");
+        if (reinterpret_cast<uintptr_t>(workspace) & 255)
+            return fail(OZEMU_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+    }
+    if (dx_zero)
+        if (ozemu_status s = hip_check(launch_zero_c(st, m, k, dX, lddx), "zero dX")) return s;
+    if (dw_zero)
+        if (ozemu_status s = hip_check(launch_zero_c(st, k, n, dW, lddw), "zero dW")) return s;
+    if (!dx_run && !dw_run) return ok();
+    char* ws = static_cast<char*>(workspace);
+    int32_t* s2 = reinterpret_cast<int32_t*>(ws + L.shift_dx);
+    int32_t* t3 = reinterpret_cast<int32_t*>(ws + L.shift_dw);
+    int32_t* zeros = reinterpret_cast<int32_t*>(ws + L.zeros);
+    int8_t* fresh = reinterpret_cast<int8_t*>(ws + L.planes_fresh);
+    int8_t* tr = reinterpret_cast<int8_t*>(ws + L.planes_t);
+    uint8_t* z = reinterpret_cast<uint8_t*>(ws + L.residues);
+    const int64_t mp = round_up(m, kTileM), np = round_up(n, kTileN), kp = round_up(k, kTileM);
+    const int64_t kp64 = round_up(k, kTileK);
+    ozemu_status s = hip_check(launch_fill_i32(st, kp, 0, zeros), "zeros");
+    if (!s && dx_run) {
+        // dX = dY W^T: rows of dY folded by 2^-t, cached W planes transposed
+        const bool big = beta_dx > 63;
+        s = hip_check(launch_scale_rows(st, m, n, dY, lddy, s2, shift_w), "scale_rows dY");
+        if (!s) s = hip_check(launch_keys_to_shifts(st, m, s2, beta_dx, nullptr), "shifts dY");
+        if (!s)
+            s = hip_check(launch_encode_a(st, p.mod, m, n, dY, lddy, s2, mp, np, fresh, big, shift_w),
+                          "encode dY");
+        if (!s)
+            s = hip_check(launch_transpose_planes(st, p.n, np, kp64, kp, planes_w, tr),
+                          "transpose W planes");
+        if (!s) s = hip_check(launch_residue_gemm(st, p.mod, mp, kp, np, fresh, tr, z), "gemm dX");
+        if (!s)
+            s = hip_check(launch_reconstruct(st, p.crt, m, k, mp, kp, z, s2, zeros, dX, lddx),
+                          "reconstruct dX");
+    }
+    if (!s && dw_run) {
+        // dW = X^T dY: columns of dY folded by 2^-s, cached X planes transposed
+        const bool big = beta_dw > 63;
+        s = hip_check(launch_scale_cols(st, m, n, dY, lddy, t3, shift_x), "scale_cols dY");
+        if (!s) s = hip_check(launch_keys_to_shifts(st, n, t3, beta_dw, nullptr), "shifts dY");
+        if (!s)
+            s = hip_check(launch_encode_b(st, p.mod, m, n, dY, lddy, t3, np, mp, fresh, big, shift_x),
+                          "encode dY");
+        if (!s)
+            s = hip_check(launch_transpose_planes(st, p.n, mp, kp64, kp, planes_x, tr),
+                          "transpose X planes");
+        if (!s) s = hip_check(launch_residue_gemm(st, p.mod, kp, np, mp, tr, fresh, z), "gemm dW");
+        if (!s)
+            s = hip_check(launch_reconstruct(st, p.crt, k, n, kp, np, z, zeros, t3, dW, lddw),
+                          "reconstruct dW");
+    }
+    return s;
 }
 
 }  // extern "C"

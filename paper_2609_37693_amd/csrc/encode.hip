@@ -70,6 +70,18 @@ __device__ __forceinline__ int8_t entry_residue(const Entry& e, const ModConsts&
     return (int8_t)v;
 }
 
+// Shift of an entry whose row (or column) shift is s and whose inner index
+// carries the fold f: s - f, the marker if either is the marker.
+template <bool kFold>
+__device__ __forceinline__ int32_t entry_shift(int32_t s, const int32_t* fold, int64_t h) {
+    if constexpr (!kFold) {
+        return s;
+    } else {
+        const int32_t f = fold[h];
+        return (s == kShiftNonFinite || f == kShiftNonFinite) ? kShiftNonFinite : s - f;
+    }
+}
+
 __device__ __forceinline__ uint32_t pack4(const int8_t* v) {
     return (uint32_t)(uint8_t)v[0] | ((uint32_t)(uint8_t)v[1] << 8) |
            ((uint32_t)(uint8_t)v[2] << 16) | ((uint32_t)(uint8_t)v[3] << 24);
@@ -89,10 +101,11 @@ __device__ __forceinline__ void fill_p2(const ModConsts& mc, uint8_t* p2) {
 
 // grid: (m_pad, ceil(k_pad / (kEncThreads * kEncVec))). Thread handles
 // columns [h, h + 16) of row i.
-template <bool kBig>
+template <bool kBig, bool kFold>
 __global__ __launch_bounds__(kEncThreads) void encode_a_kernel(ModConsts mc, int64_t m, int64_t k,
                                                                const double* A, int64_t lda,
                                                                const int32_t* shift_a,
+                                                               const int32_t* fold,
                                                                int64_t m_pad, int64_t k_pad,
                                                                int8_t* planes) {
     __shared__ uint8_t p2[kBig ? kMaxModuli * kMaxShift : 1];
@@ -108,14 +121,15 @@ __global__ __launch_bounds__(kEncThreads) void encode_a_kernel(ModConsts mc, int
 #pragma unroll
         for (int q = 0; q < kEncVec / 2; ++q) {
             double2 v = p2v[q];
-            ent[2 * q] = make_entry<kBig>(v.x, s);
-            ent[2 * q + 1] = make_entry<kBig>(v.y, s);
+            ent[2 * q] = make_entry<kBig>(v.x, entry_shift<kFold>(s, fold, h + 2 * q));
+            ent[2 * q + 1] = make_entry<kBig>(v.y, entry_shift<kFold>(s, fold, h + 2 * q + 1));
         }
     } else {
 #pragma unroll
         for (int q = 0; q < kEncVec; ++q) {
-            double v = (i < m && h + q < k) ? row[h + q] : 0.0;
-            ent[q] = make_entry<kBig>(v, s);
+            const bool in = i < m && h + q < k;
+            double v = in ? row[h + q] : 0.0;
+            ent[q] = make_entry<kBig>(v, in ? entry_shift<kFold>(s, fold, h + q) : 0);
         }
     }
     const int64_t plane_stride = m_pad * k_pad;
@@ -141,10 +155,11 @@ __global__ __launch_bounds__(kEncThreads) void encode_a_kernel(ModConsts mc, int
 constexpr int kTB = 64;
 constexpr int kLdsRow = kTB + 16;  // bytes; padding spreads rows over banks
 
-template <bool kBig>
+template <bool kBig, bool kFold>
 __global__ __launch_bounds__(kEncThreads) void encode_b_kernel(ModConsts mc, int64_t k, int64_t n,
                                                                const double* B, int64_t ldb,
                                                                const int32_t* shift_b,
+                                                               const int32_t* fold,
                                                                int64_t n_pad, int64_t k_pad,
                                                                int8_t* planes) {
     __shared__ __align__(16) int8_t tile[kTB * kLdsRow];
@@ -160,8 +175,9 @@ __global__ __launch_bounds__(kEncThreads) void encode_b_kernel(ModConsts mc, int
 #pragma unroll
     for (int q = 0; q < kEncVec; ++q) {
         const int64_t h = h0 + hq * kEncVec + q;
-        double v = (j < n && h < k) ? B[h * ldb + j] : 0.0;
-        ent[q] = make_entry<kBig>(v, s);
+        const bool in = j < n && h < k;
+        double v = in ? B[h * ldb + j] : 0.0;
+        ent[q] = make_entry<kBig>(v, in ? entry_shift<kFold>(s, fold, h) : 0);
     }
     const int64_t plane_stride = n_pad * k_pad;
     const int orow = threadIdx.x >> 2;    // output column of B (row of the plane)
@@ -188,30 +204,34 @@ __global__ __launch_bounds__(kEncThreads) void encode_b_kernel(ModConsts mc, int
 
 hipError_t launch_encode_a(hipStream_t st, const ModConsts& mc, int64_t m, int64_t k,
                            const double* A, int64_t lda, const int32_t* shift_a, int64_t m_pad,
-                           int64_t k_pad, int8_t* planes_a, bool big) {
+                           int64_t k_pad, int8_t* planes_a, bool big, const int32_t* fold) {
     if (m_pad <= 0 || k_pad <= 0) return hipSuccess;
     const int64_t per_block = (int64_t)kEncThreads * kEncVec;
     dim3 grid((unsigned)m_pad, (unsigned)((k_pad + per_block - 1) / per_block));
+    auto go = [&](auto kernel) {
+        kernel<<<grid, dim3(kEncThreads), 0, st>>>(mc, m, k, A, lda, shift_a, fold, m_pad, k_pad,
+                                                   planes_a);
+    };
     if (big)
-        encode_a_kernel<true><<<grid, dim3(kEncThreads), 0, st>>>(mc, m, k, A, lda, shift_a, m_pad,
-                                                                  k_pad, planes_a);
+        fold ? go(encode_a_kernel<true, true>) : go(encode_a_kernel<true, false>);
     else
-        encode_a_kernel<false><<<grid, dim3(kEncThreads), 0, st>>>(mc, m, k, A, lda, shift_a, m_pad,
-                                                                   k_pad, planes_a);
+        fold ? go(encode_a_kernel<false, true>) : go(encode_a_kernel<false, false>);
     return hipGetLastError();
 }
 
 hipError_t launch_encode_b(hipStream_t st, const ModConsts& mc, int64_t k, int64_t n,
                            const double* B, int64_t ldb, const int32_t* shift_b, int64_t n_pad,
-                           int64_t k_pad, int8_t* planes_b, bool big) {
+                           int64_t k_pad, int8_t* planes_b, bool big, const int32_t* fold) {
     if (n_pad <= 0 || k_pad <= 0) return hipSuccess;
     dim3 grid((unsigned)(n_pad / kTB), (unsigned)(k_pad / kTB));
+    auto go = [&](auto kernel) {
+        kernel<<<grid, dim3(kEncThreads), 0, st>>>(mc, k, n, B, ldb, shift_b, fold, n_pad, k_pad,
+                                                   planes_b);
+    };
     if (big)
-        encode_b_kernel<true><<<grid, dim3(kEncThreads), 0, st>>>(mc, k, n, B, ldb, shift_b, n_pad,
-                                                                  k_pad, planes_b);
+        fold ? go(encode_b_kernel<true, true>) : go(encode_b_kernel<true, false>);
     else
-        encode_b_kernel<false><<<grid, dim3(kEncThreads), 0, st>>>(mc, k, n, B, ldb, shift_b, n_pad,
-                                                                   k_pad, planes_b);
+        fold ? go(encode_b_kernel<false, true>) : go(encode_b_kernel<false, false>);
     return hipGetLastError();
 }
 

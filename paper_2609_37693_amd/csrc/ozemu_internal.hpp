@@ -203,20 +203,34 @@ __host__ __device__ __forceinline__ uint32_t trunc_residue(uint64_t mant, int sh
 
 // Launchers (defined in the .hip files). All take the caller's stream and
 // return hipSuccess or the launch error.
+// Row / column keys. A non-null `fold` (k entries) counts entry (i, h) of
+// A as A_ih 2^-fold[h] (rows), entry (h, j) of B as B_hj 2^-fold[h]
+// (columns): the power-of-two fold of cached shifts used by the backward.
 hipError_t launch_scale_rows(hipStream_t st, int64_t m, int64_t k, const double* A, int64_t lda,
-                             int32_t* key_a);
+                             int32_t* key_a, const int32_t* fold = nullptr);
 hipError_t launch_scale_cols(hipStream_t st, int64_t k, int64_t n, const double* B, int64_t ldb,
-                             int32_t* key_b);
+                             int32_t* key_b, const int32_t* fold = nullptr);
 hipError_t launch_keys_to_shifts(hipStream_t st, int64_t count, int32_t* key_to_shift, int beta,
                                  const int32_t* beta_per_entry);
 // Encode: `big` selects the form for kept bits above 63 (left shifts of
-// more than 10 bits), required for the bound-adaptive mode.
+// more than 10 bits), required for the bound-adaptive mode. A non-null
+// `fold` (k entries) subtracts fold[h] from the shift of every entry with
+// inner index h, as in launch_scale_rows / launch_scale_cols.
 hipError_t launch_encode_a(hipStream_t st, const ModConsts& mc, int64_t m, int64_t k,
                            const double* A, int64_t lda, const int32_t* shift_a, int64_t m_pad,
-                           int64_t k_pad, int8_t* planes_a, bool big);
+                           int64_t k_pad, int8_t* planes_a, bool big,
+                           const int32_t* fold = nullptr);
 hipError_t launch_encode_b(hipStream_t st, const ModConsts& mc, int64_t k, int64_t n,
                            const double* B, int64_t ldb, const int32_t* shift_b, int64_t n_pad,
-                           int64_t k_pad, int8_t* planes_b, bool big);
+                           int64_t k_pad, int8_t* planes_b, bool big,
+                           const int32_t* fold = nullptr);
+// Transpose block-ordered planes: `in` holds `planes` planes of
+// in_rows_pad x in_k_pad, `out` gets out_rows_pad x in_rows_pad with
+// out(r, h) = in(h, r); rows r >= in_k_pad are zero. out_rows_pad is a
+// multiple of 256 not below in_k_pad.
+hipError_t launch_transpose_planes(hipStream_t st, int planes, int64_t in_rows_pad,
+                                   int64_t in_k_pad, int64_t out_rows_pad, const int8_t* in,
+                                   int8_t* out);
 hipError_t launch_residue_gemm(hipStream_t st, const ModConsts& mc, int64_t m_pad, int64_t n_pad,
                                int64_t k_pad, const int8_t* planes_a, const int8_t* planes_b,
                                uint8_t* residues);

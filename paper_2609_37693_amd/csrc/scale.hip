@@ -19,9 +19,27 @@ __device__ __forceinline__ int32_t wave_max(int32_t v) {
     return v;
 }
 
+// Key of x * 2^-fold: the frexp exponent drops by fold exactly; a fold
+// holding the non-finite marker makes the entry non-finite.
+template <bool kFold>
+__device__ __forceinline__ int32_t folded_key(double x, const int32_t* fold, int64_t idx) {
+    const int32_t key = entry_key(__double_as_longlong(x));
+    if constexpr (!kFold) {
+        return key;
+    } else {
+        const int32_t f = fold[idx];
+        if (f == kShiftNonFinite) return kKeyNonFinite;
+        return (key == kKeyZero || key == kKeyNonFinite) ? key : key - f;
+    }
+}
+
 // One workgroup per row; each thread strides the row with 16-byte loads.
+// With kFold, entry h counts as A_ih * 2^-fold[h] (a power-of-two column
+// scaling applied without rounding).
+template <bool kFold>
 __global__ __launch_bounds__(kScaleThreads) void scale_rows_kernel(int64_t k, const double* A,
-                                                                   int64_t lda, int32_t* key_a) {
+                                                                   int64_t lda, const int32_t* fold,
+                                                                   int32_t* key_a) {
     const int64_t i = blockIdx.x;
     const double* row = A + i * lda;
     int32_t key = kKeyZero;
@@ -31,13 +49,13 @@ __global__ __launch_bounds__(kScaleThreads) void scale_rows_kernel(int64_t k, co
         const double2* r2 = reinterpret_cast<const double2*>(row);
         for (int64_t h = threadIdx.x; h < k2; h += kScaleThreads) {
             double2 v = r2[h];
-            key = max(key, entry_key(__double_as_longlong(v.x)));
-            key = max(key, entry_key(__double_as_longlong(v.y)));
+            key = max(key, folded_key<kFold>(v.x, fold, 2 * h));
+            key = max(key, folded_key<kFold>(v.y, fold, 2 * h + 1));
         }
-        if ((k & 1) && threadIdx.x == 0) key = max(key, entry_key(__double_as_longlong(row[k - 1])));
+        if ((k & 1) && threadIdx.x == 0) key = max(key, folded_key<kFold>(row[k - 1], fold, k - 1));
     } else {
         for (int64_t h = threadIdx.x; h < k; h += kScaleThreads)
-            key = max(key, entry_key(__double_as_longlong(row[h])));
+            key = max(key, folded_key<kFold>(row[h], fold, h));
     }
     key = wave_max(key);
     __shared__ int32_t part[kScaleThreads / 64];
@@ -53,15 +71,18 @@ __global__ __launch_bounds__(kScaleThreads) void scale_rows_kernel(int64_t k, co
 constexpr int kColRows = 64;  // rows of B per workgroup slab
 
 // grid: (ceil(n / 256), ceil(k / kColRows)); key_b pre-filled with kKeyZero.
+// With kFold, entry (h, j) counts as B_hj * 2^-fold[h].
+template <bool kFold>
 __global__ __launch_bounds__(kScaleThreads) void scale_cols_kernel(int64_t k, int64_t n,
                                                                    const double* B, int64_t ldb,
+                                                                   const int32_t* fold,
                                                                    int32_t* key_b) {
     const int64_t j = (int64_t)blockIdx.x * kScaleThreads + threadIdx.x;
     if (j >= n) return;
     const int64_t h0 = (int64_t)blockIdx.y * kColRows;
     const int64_t h1 = min(k, h0 + kColRows);
     int32_t key = kKeyZero;
-    for (int64_t h = h0; h < h1; ++h) key = max(key, entry_key(__double_as_longlong(B[h * ldb + j])));
+    for (int64_t h = h0; h < h1; ++h) key = max(key, folded_key<kFold>(B[h * ldb + j], fold, h));
     if (key != kKeyZero) atomicMax(key_b + j, key);
 }
 
@@ -161,9 +182,14 @@ __global__ void bound_shifts_kernel(int64_t count, const int32_t* key, const int
 }  // namespace
 
 hipError_t launch_scale_rows(hipStream_t st, int64_t m, int64_t k, const double* A, int64_t lda,
-                             int32_t* key_a) {
+                             int32_t* key_a, const int32_t* fold) {
     if (m <= 0) return hipSuccess;
-    scale_rows_kernel<<<dim3((unsigned)m), dim3(kScaleThreads), 0, st>>>(k, A, lda, key_a);
+    if (fold)
+        scale_rows_kernel<true><<<dim3((unsigned)m), dim3(kScaleThreads), 0, st>>>(k, A, lda, fold,
+                                                                                   key_a);
+    else
+        scale_rows_kernel<false><<<dim3((unsigned)m), dim3(kScaleThreads), 0, st>>>(k, A, lda,
+                                                                                    nullptr, key_a);
     return hipGetLastError();
 }
 
@@ -174,13 +200,16 @@ hipError_t launch_fill_i32(hipStream_t st, int64_t count, int32_t value, int32_t
 }
 
 hipError_t launch_scale_cols(hipStream_t st, int64_t k, int64_t n, const double* B, int64_t ldb,
-                             int32_t* key_b) {
+                             int32_t* key_b, const int32_t* fold) {
     if (n <= 0) return hipSuccess;
     hipError_t e = launch_fill_i32(st, n, kKeyZero, key_b);
     if (e != hipSuccess || k <= 0) return e;
     dim3 grid((unsigned)((n + kScaleThreads - 1) / kScaleThreads),
               (unsigned)((k + kColRows - 1) / kColRows));
-    scale_cols_kernel<<<grid, dim3(kScaleThreads), 0, st>>>(k, n, B, ldb, key_b);
+    if (fold)
+        scale_cols_kernel<true><<<grid, dim3(kScaleThreads), 0, st>>>(k, n, B, ldb, fold, key_b);
+    else
+        scale_cols_kernel<false><<<grid, dim3(kScaleThreads), 0, st>>>(k, n, B, ldb, nullptr, key_b);
     return hipGetLastError();
 }
 

@@ -116,10 +116,10 @@ def test_host_side_errors_before_launch():
     # missing or short workspace
     assert _call_dgemm(plan, 8, 8, 8) == S.OZEMU_ERR_WORKSPACE
     assert _call_dgemm(plan, 8, 8, 8, ws=256, ws_bytes=16) == S.OZEMU_ERR_WORKSPACE
+    assert "workspace" in _lib.load().ozemu_last_error().decode()
     # empty output is a no-op that touches nothing
     assert _call_dgemm(plan, 0, 8, 8, A=0, B=0, C_=0) == S.OZEMU_OK
     assert _call_dgemm(plan, 8, 0, 8, A=0, B=0, C_=0) == S.OZEMU_OK
-    assert "workspace" in _lib.load().ozemu_last_error().decode() or True
 
 
 def test_f53_refuses_k_above_reconstruction_cap():
@@ -135,3 +135,58 @@ def test_status_strings():
     assert lib.ozemu_status_string(0) == b"OZEMU_OK"
     assert lib.ozemu_status_string(-2) == b"OZEMU_ERR_K_TOO_LARGE"
     assert lib.ozemu_version().startswith(b"ozemu")
+
+
+def _p(v):
+    return C.c_void_p(v) if v else C.c_void_p()
+
+
+def _call_fwd_cache(plan, m, n, k, X=1, W=1, Y=1, cache=1, ws=None, ws_bytes=0):
+    lib = _lib.load()
+    return lib.ozemu_dgemm_fwd_cache(plan.handle, None, m, n, k, _p(X), k, _p(W), n, _p(Y), n,
+                                     _p(cache), _p(cache), _p(cache), _p(cache), _p(ws), ws_bytes)
+
+
+def _call_bwd(plan, m, n, k, dY=1, cache=1, dX=1, dW=1, lddx=None, lddw=None, ws=None,
+              ws_bytes=0):
+    lib = _lib.load()
+    return lib.ozemu_dgemm_bwd(plan.handle, None, m, n, k, _p(dY), n, _p(cache), _p(cache),
+                               _p(cache), _p(cache), _p(dX), lddx if lddx is not None else k,
+                               _p(dW), lddw if lddw is not None else n, _p(ws), ws_bytes)
+
+
+def test_cached_forward_and_backward_host_errors():
+    S = _lib
+    w = oz.Plan(num_moduli=16, scaling="W")
+    # the caps apply at max(m, n, k): a batch above the accumulation cap is refused
+    assert _call_fwd_cache(w, 131072, 8, 8) == S.OZEMU_ERR_K_TOO_LARGE
+    assert _call_bwd(w, 8, 131072, 8) == S.OZEMU_ERR_K_TOO_LARGE
+    assert _call_fwd_cache(w, 8, 8, 8) == S.OZEMU_ERR_WORKSPACE
+    assert _call_fwd_cache(w, 8, 8, 8, cache=0) == S.OZEMU_ERR_INVALID_ARG
+    assert _call_bwd(w, 8, 8, 8) == S.OZEMU_ERR_WORKSPACE
+    assert _call_bwd(w, 8, 8, 8, cache=0) == S.OZEMU_ERR_INVALID_ARG
+    assert _call_bwd(w, 8, 8, 8, dY=0) == S.OZEMU_ERR_INVALID_ARG
+    assert _call_bwd(w, 8, 8, 8, lddx=7) == S.OZEMU_ERR_INVALID_ARG
+    assert _call_bwd(w, 8, 8, 8, lddw=7) == S.OZEMU_ERR_INVALID_ARG
+    # nothing asked for, or nothing to compute: no-ops
+    assert _call_bwd(w, 8, 8, 8, dX=0, dW=0, dY=0, cache=0) == S.OZEMU_OK
+    assert _call_bwd(w, 8, 8, 0, dY=0, cache=0) == S.OZEMU_OK
+    assert _call_fwd_cache(w, 0, 8, 8, X=0, W=0, Y=0, cache=0) == S.OZEMU_OK
+    # the bound-adaptive mode has no cached variant
+    g = oz.Plan(num_moduli=16, scaling="G")
+    assert _call_fwd_cache(g, 8, 8, 8) == S.OZEMU_ERR_UNSUPPORTED
+    assert _call_bwd(g, 8, 8, 8) == S.OZEMU_ERR_UNSUPPORTED
+    # F53: the reconstruction cap at 53 + 53 bits applies at max(m, n, k)
+    f = oz.Plan(num_moduli=14, scaling="F53")
+    assert _call_fwd_cache(f, 4, 4, 10) == S.OZEMU_ERR_WORKSPACE
+    assert _call_fwd_cache(f, 11, 4, 4) == S.OZEMU_ERR_K_TOO_LARGE
+
+
+def test_backward_workspace_covers_both_products():
+    plan = oz.Plan(num_moduli=14, scaling="W")
+    m, n, k = 300, 200, 100
+    mp, np_, kp = 512, 256, 256
+    v = C.c_size_t()
+    _lib.check(_lib.load().ozemu_bwd_workspace_size(plan.handle, m, n, k, C.byref(v)))
+    # fresh dY planes, transposed cached planes, residues of the larger product
+    assert v.value >= 14 * (mp * np_ + kp * max(mp, np_) + kp * max(mp, np_))
