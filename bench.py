@@ -42,6 +42,11 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=32,
                     help="rows of C in the CPU oracle's bounded sample")
     ap.add_argument("--no-native", action="store_true")
+    ap.add_argument("--workload", default="dgemm", choices=["dgemm", "mlp"],
+                    help="dgemm: the 8192^3 emulated DGEMM (default); mlp: one training "
+                         "step of a 4-layer tanh MLP through the cached-residue backward")
+    ap.add_argument("--batch", type=int, default=8192)
+    ap.add_argument("--width", type=int, default=4096)
     return ap.parse_args()
 
 
@@ -114,6 +119,69 @@ def cpu_baseline(A, B, moduli, mode, rows):
                                                                  platform.machine())}
 
 
+def mlp_main(args):
+    """One training step of a 4-layer FP64 MLP (no bias, tanh between
+    layers, loss 1/2 ||H_4 - T||^2): forward through the cached-residue
+    emulated product, backward dX = dY W^T and dW = X^T dY through the
+    cached planes. Twelve products of batch x width x width per step."""
+    import torch
+    import paper_2609_37693_amd as oz
+    from paper_2609_37693_amd.autograd import emulated_matmul
+    from workloads import phi_matrix
+
+    B, Wd = args.batch, args.width
+    X = torch.from_numpy(phi_matrix(B, Wd, 1.0, args.seed)).cuda()
+    T = torch.from_numpy(np.random.default_rng(args.seed + 5).standard_normal((B, Wd))).cuda()
+    Ws = [torch.from_numpy(phi_matrix(Wd, Wd, 1.0, args.seed + 10 + i) * 2.0 ** -6).cuda()
+          .requires_grad_() for i in range(4)]
+    plan = oz.Plan(num_moduli=args.moduli, scaling="W")
+
+    def step(emulated=True):
+        for w in Ws:
+            w.grad = None
+        h = X
+        for i, w in enumerate(Ws):
+            h = emulated_matmul(h, w, plan) if emulated else h @ w
+            if i < 3:
+                h = torch.tanh(h)
+        loss = 0.5 * ((h - T) ** 2).sum()
+        loss.backward()
+        return loss
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    flops = 12 * 2.0 * B * Wd * Wd
+    g_emu = [w.grad.clone() for w in Ws]
+    native_ms = time_stream(lambda: step(False), max(3, args.steps // 2), 1)
+    step(False)
+    torch.cuda.synchronize()
+    rel = max(float(torch.linalg.norm(a - w.grad) / torch.linalg.norm(w.grad))
+              for a, w in zip(g_emu, Ws))
+    out = {
+        "metric": "emulated FP64 MLP training step TFLOP/s (forward + cached-residue backward)",
+        "value": flops / (ms * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": "4-layer tanh MLP, batch %d, width %d, FP64, %d moduli, "
+                               "cached-residue backward" % (B, Wd, args.moduli),
+                   "batch": B, "width": Wd, "moduli": args.moduli},
+        "native_fp64": {"ms": native_ms, "value": flops / (native_ms * 1e-3) / 1e12},
+        "speedup_vs_native": native_ms / ms,
+        "max_rel_frobenius_grad_vs_native": rel,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -121,6 +189,11 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.workload == "mlp":
+        if not torch.cuda.is_available():
+            print("no HIP device", file=sys.stderr)
+            sys.exit(1)
+        return mlp_main(args)
     import paper_2609_37693_amd as oz
     from workloads import operand_pair
 
