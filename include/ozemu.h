@@ -205,6 +205,43 @@ ozemu_status ozemu_dgemm_bwd(ozemu_plan plan, void* stream, int64_t m, int64_t n
                              const int8_t* planes_w, double* dX, int64_t lddx, double* dW,
                              int64_t lddw, void* workspace, size_t ws_bytes);
 
+/* ---- Grouped products: many independent C_p = A_p B_p of different shapes
+ * and plans in one set of launches (the paper treats one product at a time).
+ * Scale, Reduce and Reconstruct run over the work of all problems at once;
+ * the residue GEMM is one persistent launch whose workgroups take
+ * (problem, modulus, tile) items from a counter, longest K first. A group
+ * fixes shapes, plans and operand pointers; running it issues one
+ * host-to-device copy of the group's tables (from pinned host memory the
+ * group owns) and kernels, so a run can be captured in a HIP graph. ---- */
+typedef struct ozemu_group_s* ozemu_group;
+
+/* Build a group of `count` (0..4096) problems. Host arrays of length count:
+ * plans[p] (a plan per problem, repeats allowed, F53 or WINDOW; the group
+ * copies what it needs, so plans may be destroyed afterwards), shapes
+ * m/n/k, device pointers A/B/C with leading dimensions (row-major, as for
+ * ozemu_dgemm; pointers of empty problems are ignored). Each problem is
+ * validated as ozemu_dgemm validates it (the message names the problem).
+ * Host memory only. */
+ozemu_status ozemu_group_create(ozemu_group* out, int count, const ozemu_plan* plans,
+                                const int64_t* m, const int64_t* n, const int64_t* k,
+                                const double* const* A, const int64_t* lda,
+                                const double* const* B, const int64_t* ldb, double* const* C,
+                                const int64_t* ldc);
+
+/* Bytes of device workspace ozemu_group_run needs (tables, then every
+ * problem's shifts, planes and residues). */
+ozemu_status ozemu_group_workspace_size(ozemu_group group, size_t* bytes);
+
+/* C_p = A_p B_p for every problem (results as ozemu_dgemm with the
+ * problem's plan). `workspace`: ozemu_group_workspace_size bytes, 256-byte
+ * aligned. The first run of a group makes the pinned host copy of its
+ * tables (hipHostMalloc), so run once before capturing a run in a graph.
+ * Runs of one group or workspace on different streams race. */
+ozemu_status ozemu_group_run(ozemu_group group, void* stream, void* workspace, size_t ws_bytes);
+
+/* Free the group; work launched by ozemu_group_run must have completed. */
+ozemu_status ozemu_group_destroy(ozemu_group group);
+
 const char* ozemu_status_string(int status);
 const char* ozemu_last_error(void);
 const char* ozemu_version(void);

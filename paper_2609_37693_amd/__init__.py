@@ -16,7 +16,8 @@ from . import _lib
 from ._lib import OzemuError, SCALING, SHIFT_NONFINITE
 
 __all__ = ["Plan", "dgemm", "scale", "reduce", "residue_gemm", "reconstruct", "OzemuError",
-           "SHIFT_NONFINITE", "version", "ForwardCache", "dgemm_fwd_cache", "dgemm_bwd"]
+           "SHIFT_NONFINITE", "version", "ForwardCache", "dgemm_fwd_cache", "dgemm_bwd", "Group",
+           "dgemm_grouped"]
 
 
 def version() -> str:
@@ -281,3 +282,83 @@ def dgemm_bwd(dY, cache: ForwardCache, need_dx: bool = True, need_dw: bool = Tru
         _ptr(cache.shift_w), _ptr(cache.planes_x), _ptr(cache.planes_w),
         _ptr(dX), lddx, _ptr(dW), lddw, _ptr(workspace), workspace.numel()))
     return dX, dW
+
+
+class Group:
+    """Many independent products C_p = A_p @ B_p (different shapes and plans)
+    run as one set of launches: ozemu_group_create / ozemu_group_run. The
+    group binds the operand and output tensors (kept alive here); ``run``
+    is capturable in a HIP graph."""
+
+    def __init__(self, As, Bs, plans, outs=None):
+        torch = _torch()
+        count = len(As)
+        if len(Bs) != count:
+            raise ValueError("As and Bs differ in length")
+        if isinstance(plans, Plan):
+            plans = [plans] * count
+        if len(plans) != count:
+            raise ValueError("one plan per problem")
+        self.As, self.Bs, self.plans = [], [], list(plans)
+        self.outs = []
+        ms, ns, ks, lda, ldb, ldc = [], [], [], [], [], []
+        for p in range(count):
+            A, la = _matrix(As[p], "A[%d]" % p)
+            B, lb = _matrix(Bs[p], "B[%d]" % p)
+            m, k = A.shape
+            k2, n = B.shape
+            if k != k2:
+                raise ValueError("problem %d: inner dimensions differ: %d vs %d" % (p, k, k2))
+            if outs is not None:
+                Cp = outs[p]
+            else:
+                Cp = torch.empty((m, n), dtype=torch.float64, device=A.device)
+            self.As.append(A)
+            self.Bs.append(B)
+            self.outs.append(Cp)
+            ms.append(m)
+            ns.append(n)
+            ks.append(k)
+            lda.append(la)
+            ldb.append(lb)
+            ldc.append(Cp.stride(0) if Cp.numel() > 0 else max(1, n))
+        I64 = C.c_int64 * max(count, 1)
+        VP = C.c_void_p * max(count, 1)
+        self._lib = _lib.load()
+        self._h = C.c_void_p()
+        ptrs = lambda ts: VP(*[t.data_ptr() if t.numel() > 0 else None for t in ts])  # noqa: E731
+        _lib.check(self._lib.ozemu_group_create(
+            C.byref(self._h), count, VP(*[pl.handle.value for pl in self.plans]), I64(*ms),
+            I64(*ns), I64(*ks), ptrs(self.As), I64(*lda), ptrs(self.Bs), I64(*ldb),
+            ptrs(self.outs), I64(*ldc)))
+        v = C.c_size_t()
+        _lib.check(self._lib.ozemu_group_workspace_size(self._h, C.byref(v)))
+        self.workspace_bytes = v.value
+        self.device = self.As[0].device if count else None
+        self.workspace = None
+
+    def run(self, workspace=None):
+        """Launch every product on torch's current stream; returns the outputs."""
+        torch = _torch()
+        if workspace is None:
+            if self.workspace is None:
+                self.workspace = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8,
+                                             device=self.device)
+            workspace = self.workspace
+        _lib.check(self._lib.ozemu_group_run(self._h, _stream_ptr(), _ptr(workspace),
+                                             workspace.numel()))
+        return self.outs
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                _torch().cuda.synchronize()
+            finally:
+                self._lib.ozemu_group_destroy(h)
+                self._h = None
+
+
+def dgemm_grouped(As, Bs, plans):
+    """[A_p @ B_p] for every p, emulated as one grouped launch."""
+    return Group(As, Bs, plans).run()

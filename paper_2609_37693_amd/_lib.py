@@ -51,6 +51,13 @@ SIGNATURES = {
     "ozemu_bwd_workspace_size": (_st, [_vp, _i64, _i64, _i64, C.POINTER(C.c_size_t)]),
     "ozemu_dgemm_bwd": (_st, [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp,
                               _i64, _vp, _i64, _vp, C.c_size_t]),
+    "ozemu_group_create": (_st, [C.POINTER(_vp), C.c_int, C.POINTER(_vp), C.POINTER(_i64),
+                                 C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_vp),
+                                 C.POINTER(_i64), C.POINTER(_vp), C.POINTER(_i64),
+                                 C.POINTER(_vp), C.POINTER(_i64)]),
+    "ozemu_group_workspace_size": (_st, [_vp, C.POINTER(C.c_size_t)]),
+    "ozemu_group_run": (_st, [_vp, _vp, _vp, C.c_size_t]),
+    "ozemu_group_destroy": (_st, [_vp]),
     "ozemu_status_string": (C.c_char_p, [C.c_int]),
     "ozemu_last_error": (C.c_char_p, []),
     "ozemu_version": (C.c_char_p, []),

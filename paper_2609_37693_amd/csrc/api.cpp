@@ -18,6 +18,18 @@ struct ozemu_plan_s {
     ozemu::Plan p;
 };
 
+// A grouped product: per-problem descriptors, plan constants and work
+// prefixes, laid out as they are copied to the start of the workspace.
+struct ozemu_group_s {
+    int count = 0, nplans = 0, dmax = 2;
+    size_t table_bytes = 0, ws_bytes = 0;
+    size_t off_probs = 0, off_mods = 0, off_crts = 0, off_prefix = 0, off_order = 0,
+           off_counter = 0;
+    int32_t total[ozemu::kGKinds] = {};
+    std::vector<char> tables;  // table_bytes, built at creation
+    char* pinned = nullptr;    // pinned copy for the uploads, made by the first run
+};
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -484,6 +496,233 @@ ozemu_status ozemu_dgemm(ozemu_plan plan, void* stream, int64_t m, int64_t n, in
         return s;
     return hip_check(ozemu::launch_reconstruct(st, p.crt, m, n, d.m_pad, d.n_pad, z, sa, sb, C, ldc),
                      "reconstruct");
+}
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+int32_t cdiv32(int64_t a, int64_t b) { return (int32_t)((a + b - 1) / b); }
+
+}  // namespace
+
+ozemu_status ozemu_group_create(ozemu_group* out, int count, const ozemu_plan* plans,
+                                const int64_t* m, const int64_t* n, const int64_t* k,
+                                const double* const* A, const int64_t* lda,
+                                const double* const* B, const int64_t* ldb, double* const* C,
+                                const int64_t* ldc) {
+    using namespace ozemu;
+    if (!out) return fail(OZEMU_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (count < 0 || count > kMaxGroup)
+        return fail(OZEMU_ERR_INVALID_ARG, "count must be in [0, 4096]");
+    if (count > 0 && (!plans || !m || !n || !k || !A || !lda || !B || !ldb || !C || !ldc))
+        return fail(OZEMU_ERR_INVALID_ARG, "NULL host array");
+    // distinct plans, in first-use order
+    std::vector<const ozemu::Plan*> uniq;
+    std::vector<int32_t> pidx(count);
+    for (int p = 0; p < count; ++p) {
+        if (!plans[p]) return fail(OZEMU_ERR_INVALID_ARG, "plan of problem " + std::to_string(p) + " is NULL");
+        const Plan* pl = &plans[p]->p;
+        if (pl->scaling == OZEMU_SCALE_BOUND)
+            return fail(OZEMU_ERR_UNSUPPORTED, "grouped products support F53 and WINDOW");
+        int at = -1;
+        for (size_t u = 0; u < uniq.size(); ++u)
+            if (uniq[u] == pl) at = (int)u;
+        if (at < 0) {
+            at = (int)uniq.size();
+            uniq.push_back(pl);
+        }
+        pidx[p] = at;
+    }
+    std::vector<GProblem> probs(count);
+    for (int p = 0; p < count; ++p) {
+        const Plan& pl = *uniq[pidx[p]];
+        const std::string where = " (problem " + std::to_string(p) + ")";
+        if (ozemu_status st = check_shape(pl, m[p], n[p], k[p])) {
+            g_last_error += where;
+            return st;
+        }
+        GProblem& P = probs[p];
+        P.m = m[p];
+        P.n = n[p];
+        P.k = k[p];
+        const bool active = m[p] > 0 && n[p] > 0;
+        if (active) {
+            if (ozemu_status st = check_operands(m[p], n[p], k[p], A[p], lda[p], B[p], ldb[p])) {
+                g_last_error += where;
+                return st;
+            }
+            if (!C[p] || ldc[p] < n[p])
+                return fail(OZEMU_ERR_INVALID_ARG, "C is NULL or ldc < n" + where);
+        }
+        Dims d = dims_of(m[p], n[p], k[p]);
+        P.m_pad = d.m_pad;
+        P.n_pad = d.n_pad;
+        P.k_pad = d.k_pad;
+        P.A = A[p];
+        P.B = B[p];
+        P.C = C[p];
+        P.lda = lda[p];
+        P.ldb = ldb[p];
+        P.ldc = ldc[p];
+        P.plan = pidx[p];
+        int ba = 0, bb = 0;
+        if (k[p] > 0) kept_bits_of(pl, k[p], ba, bb);
+        P.beta_a = ba;
+        P.beta_b = bb;
+        P.big = (ba > 63 || bb > 63) ? 1 : 0;
+    }
+    ozemu_group g = new (std::nothrow) ozemu_group_s;
+    if (!g) return fail(OZEMU_ERR_INVALID_ARG, "out of host memory");
+    g->count = count;
+    g->nplans = (int)uniq.size();
+    // table layout
+    size_t off = 0;
+    g->off_probs = off;
+    off = align256(off + sizeof(GProblem) * (size_t)count);
+    g->off_mods = off;
+    off = align256(off + sizeof(ModConsts) * uniq.size());
+    g->off_crts = off;
+    off = align256(off + sizeof(CrtConsts) * uniq.size());
+    g->off_prefix = off;
+    off = align256(off + sizeof(int32_t) * (size_t)kGKinds * (count + 1));
+    g->off_order = off;
+    off = align256(off + sizeof(int32_t) * (size_t)count);
+    g->off_counter = off;
+    off = align256(off + sizeof(int32_t));
+    g->table_bytes = off;
+    // per-problem workspace regions and work prefixes
+    std::vector<int32_t> prefix((size_t)kGKinds * (count + 1), 0);
+    std::vector<int32_t> order(count);
+    for (int p = 0; p < count; ++p) order[p] = p;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return probs[a].k_pad > probs[b].k_pad; });
+    int64_t tot[kGKinds] = {};
+    for (int p = 0; p < count; ++p) {
+        GProblem& P = probs[p];
+        const size_t N = (size_t)uniq[P.plan]->n;
+        const bool active = P.m > 0 && P.n > 0;
+        const bool work = active && P.k > 0;
+        P.off_sa = (int64_t)off;
+        off = align256(off + sizeof(int32_t) * (size_t)P.m_pad);
+        P.off_sb = (int64_t)off;
+        off = align256(off + sizeof(int32_t) * (size_t)P.n_pad);
+        P.off_pa = (int64_t)off;
+        if (work) off = align256(off + N * (size_t)P.m_pad * (size_t)P.k_pad);
+        P.off_pb = (int64_t)off;
+        if (work) off = align256(off + N * (size_t)P.n_pad * (size_t)P.k_pad);
+        P.off_z = (int64_t)off;
+        if (work) off = align256(off + N * (size_t)P.m_pad * (size_t)P.n_pad);
+        int64_t blocks[kGKinds] = {};
+        if (work) {
+            blocks[kGColInit] = cdiv32(P.n, 256);
+            blocks[kGRows] = P.m;
+            blocks[kGCols] = (int64_t)cdiv32(P.n, 256) * cdiv32(P.k, 64);
+            blocks[kGShifts] = cdiv32(P.m + P.n, 256);
+            blocks[kGEncA] = P.m_pad * cdiv32(P.k_pad, 4096);
+            blocks[kGEncB] = (P.n_pad / 64) * (P.k_pad / 64);
+        }
+        if (active) blocks[kGCrt] = cdiv32(P.m * ((P.n + 3) / 4), 256);
+        for (int kind = 0; kind < kGKinds; ++kind) {
+            if (kind == kGTiles) continue;
+            prefix[(size_t)kind * (count + 1) + p] = (int32_t)tot[kind];
+            tot[kind] += blocks[kind];
+        }
+    }
+    for (int q = 0; q < count; ++q) {
+        const GProblem& P = probs[order[q]];
+        const bool work = P.m > 0 && P.n > 0 && P.k > 0;
+        prefix[(size_t)kGTiles * (count + 1) + q] = (int32_t)tot[kGTiles];
+        if (work)
+            tot[kGTiles] += (int64_t)uniq[P.plan]->n * (P.m_pad / kTileM) * (P.n_pad / kTileN);
+    }
+    for (int kind = 0; kind < kGKinds; ++kind) {
+        if (tot[kind] > INT32_MAX) {
+            delete g;
+            return fail(OZEMU_ERR_INVALID_ARG, "group too large for one launch");
+        }
+        prefix[(size_t)kind * (count + 1) + count] = (int32_t)tot[kind];
+        g->total[kind] = (int32_t)tot[kind];
+    }
+    g->ws_bytes = off;
+    g->dmax = 2;
+    for (const Plan* pl : uniq) g->dmax = std::max(g->dmax, pl->crt.d);
+    g->tables.assign(g->table_bytes, 0);
+    char* t = g->tables.data();
+    if (count > 0) std::memcpy(t + g->off_probs, probs.data(), sizeof(GProblem) * count);
+    for (size_t u = 0; u < uniq.size(); ++u) {
+        std::memcpy(t + g->off_mods + u * sizeof(ModConsts), &uniq[u]->mod, sizeof(ModConsts));
+        std::memcpy(t + g->off_crts + u * sizeof(CrtConsts), &uniq[u]->crt, sizeof(CrtConsts));
+    }
+    std::memcpy(t + g->off_prefix, prefix.data(), sizeof(int32_t) * prefix.size());
+    if (count > 0) std::memcpy(t + g->off_order, order.data(), sizeof(int32_t) * count);
+    *out = g;
+    return ok();
+}
+
+ozemu_status ozemu_group_workspace_size(ozemu_group group, size_t* bytes) {
+    if (!group) return fail(OZEMU_ERR_INVALID_ARG, "group is NULL");
+    if (!bytes) return fail(OZEMU_ERR_INVALID_ARG, "bytes is NULL");
+    *bytes = group->ws_bytes;
+    return ok();
+}
+
+ozemu_status ozemu_group_run(ozemu_group group, void* stream, void* workspace, size_t ws_bytes) {
+    using namespace ozemu;
+    if (!group) return fail(OZEMU_ERR_INVALID_ARG, "group is NULL");
+    if (group->count == 0 || (group->total[kGCrt] == 0)) return ok();
+    if (!workspace || ws_bytes < group->ws_bytes)
+        return fail(OZEMU_ERR_WORKSPACE, "workspace smaller than ozemu_group_workspace_size");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255)
+        return fail(OZEMU_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = static_cast<char*>(workspace);
+    if (!group->pinned) {
+        // pinned and never rewritten, so every run (and a captured graph's
+        // replays) can copy from it asynchronously
+        char* h = nullptr;
+        if (ozemu_status s = hip_check(hipHostMalloc((void**)&h, group->table_bytes,
+                                                     hipHostMallocDefault),
+                                       "pinned group tables"))
+            return s;
+        std::memcpy(h, group->tables.data(), group->table_bytes);
+        group->pinned = h;
+    }
+    if (ozemu_status s = hip_check(hipMemcpyAsync(ws, group->pinned, group->table_bytes,
+                                                  hipMemcpyHostToDevice, st),
+                                   "group tables"))
+        return s;
+    GroupArgs a;
+    a.probs = reinterpret_cast<const GProblem*>(ws + group->off_probs);
+    a.mods = reinterpret_cast<const ModConsts*>(ws + group->off_mods);
+    a.crts = reinterpret_cast<const CrtConsts*>(ws + group->off_crts);
+    a.prefix = reinterpret_cast<const int32_t*>(ws + group->off_prefix);
+    a.order = reinterpret_cast<const int32_t*>(ws + group->off_order);
+    a.ws = ws;
+    a.counter = reinterpret_cast<int32_t*>(ws + group->off_counter);
+    a.count = group->count;
+    const int32_t* T = group->total;
+    // one persistent GEMM workgroup per compute unit (its LDS allows one)
+    int dev = 0, workers = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&workers, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        workers <= 0)
+        workers = 256;
+    ozemu_status s = hip_check(launch_group_init(st, a, T[kGColInit]), "group init");
+    if (!s) s = hip_check(launch_group_scale(st, a, T[kGRows], T[kGCols], T[kGShifts]), "group scale");
+    if (!s) s = hip_check(launch_group_encode(st, a, T[kGEncA], T[kGEncB]), "group encode");
+    if (!s) s = hip_check(launch_group_gemm(st, a, T[kGTiles], workers), "group gemm");
+    if (!s) s = hip_check(launch_group_reconstruct(st, a, T[kGCrt], group->dmax), "group reconstruct");
+    return s;
+}
+
+ozemu_status ozemu_group_destroy(ozemu_group group) {
+    if (group) {
+        if (group->pinned) (void)hipHostFree(group->pinned);
+        delete group;
+    }
+    return ok();
 }
 
 ozemu_status ozemu_dgemm_fwd_cache(ozemu_plan plan, void* stream, int64_t m, int64_t n, int64_t k,

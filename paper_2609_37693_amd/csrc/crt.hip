@@ -99,15 +99,15 @@ __device__ __forceinline__ double finish_one(const CrtConsts& cc, int64_t* acc, 
     return neg ? -r : r;
 }
 
+// Thread g of the output: row g / ceil(n / 4), four consecutive columns.
 template <int D>
-__global__ __launch_bounds__(kThreads) void reconstruct_kernel(CrtConsts cc, int64_t m, int64_t n,
-                                                               int64_t m_pad, int64_t n_pad,
-                                                               const uint8_t* __restrict__ Z,
-                                                               const int32_t* __restrict__ sa,
-                                                               const int32_t* __restrict__ sb,
-                                                               double* __restrict__ C, int64_t ldc) {
+__device__ __forceinline__ void reconstruct_body(const CrtConsts& cc, int64_t m, int64_t n,
+                                                 int64_t m_pad, int64_t n_pad,
+                                                 const uint8_t* __restrict__ Z,
+                                                 const int32_t* __restrict__ sa,
+                                                 const int32_t* __restrict__ sb,
+                                                 double* __restrict__ C, int64_t ldc, int64_t g) {
     const int64_t per_row = (n + kPerThread - 1) / kPerThread;
-    const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (g >= m * per_row) return;
     const int64_t i = g / per_row;
     const int64_t j0 = (g % per_row) * kPerThread;
@@ -156,10 +156,48 @@ __global__ __launch_bounds__(kThreads) void reconstruct_kernel(CrtConsts cc, int
     }
 }
 
+template <int D>
+__global__ __launch_bounds__(kThreads) void reconstruct_kernel(CrtConsts cc, int64_t m, int64_t n,
+                                                               int64_t m_pad, int64_t n_pad,
+                                                               const uint8_t* __restrict__ Z,
+                                                               const int32_t* __restrict__ sa,
+                                                               const int32_t* __restrict__ sb,
+                                                               double* __restrict__ C, int64_t ldc) {
+    reconstruct_body<D>(cc, m, n, m_pad, n_pad, Z, sa, sb, C, ldc,
+                        (int64_t)blockIdx.x * kThreads + threadIdx.x);
+}
+
 __global__ void zero_c_kernel(int64_t m, int64_t n, double* C, int64_t ldc) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= m * n) return;
     C[(g / n) * ldc + g % n] = 0.0;
+}
+
+// Grouped Reconstruct; a problem with k = 0 gets zeros.
+template <int D>
+__global__ __launch_bounds__(kThreads) void group_reconstruct_kernel(GroupArgs g) {
+    const int32_t* pre = g.prefix + kGCrt * (g.count + 1);
+    const int p = group_find(pre, g.count, blockIdx.x);
+    const GProblem& P = g.probs[p];
+    const int64_t t = (int64_t)(blockIdx.x - pre[p]) * kThreads + threadIdx.x;
+    if (P.k == 0) {
+        const int64_t per_row = (P.n + kPerThread - 1) / kPerThread;
+        if (t >= P.m * per_row) return;
+        const int64_t i = t / per_row, j0 = (t % per_row) * kPerThread;
+        for (int c = 0; c < kPerThread; ++c)
+            if (j0 + c < P.n) P.C[i * P.ldc + j0 + c] = 0.0;
+        return;
+    }
+    reconstruct_body<D>(g.crts[P.plan], P.m, P.n, P.m_pad, P.n_pad,
+                        reinterpret_cast<const uint8_t*>(g.ws + P.off_z),
+                        reinterpret_cast<const int32_t*>(g.ws + P.off_sa),
+                        reinterpret_cast<const int32_t*>(g.ws + P.off_sb), P.C, P.ldc, t);
+}
+
+template <int D>
+hipError_t launch_group_d(hipStream_t st, const GroupArgs& g, int32_t blocks) {
+    group_reconstruct_kernel<D><<<dim3((unsigned)blocks), dim3(kThreads), 0, st>>>(g);
+    return hipGetLastError();
 }
 
 template <int D>
@@ -190,6 +228,22 @@ hipError_t launch_reconstruct(hipStream_t st, const CrtConsts& cc, int64_t m, in
         case 8: return launch_d<8>(st, cc, m, n, m_pad, n_pad, residues, shift_a, shift_b, C, ldc);
         case 9: return launch_d<9>(st, cc, m, n, m_pad, n_pad, residues, shift_a, shift_b, C, ldc);
         case 10: return launch_d<10>(st, cc, m, n, m_pad, n_pad, residues, shift_a, shift_b, C, ldc);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_group_reconstruct(hipStream_t st, const GroupArgs& g, int32_t blocks, int dmax) {
+    if (blocks <= 0) return hipSuccess;
+    switch (dmax) {
+        case 2: return launch_group_d<2>(st, g, blocks);
+        case 3: return launch_group_d<3>(st, g, blocks);
+        case 4: return launch_group_d<4>(st, g, blocks);
+        case 5: return launch_group_d<5>(st, g, blocks);
+        case 6: return launch_group_d<6>(st, g, blocks);
+        case 7: return launch_group_d<7>(st, g, blocks);
+        case 8: return launch_group_d<8>(st, g, blocks);
+        case 9: return launch_group_d<9>(st, g, blocks);
+        case 10: return launch_group_d<10>(st, g, blocks);
         default: return hipErrorInvalidValue;
     }
 }

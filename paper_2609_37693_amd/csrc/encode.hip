@@ -99,19 +99,18 @@ __device__ __forceinline__ void fill_p2(const ModConsts& mc, uint8_t* p2) {
     }
 }
 
-// grid: (m_pad, ceil(k_pad / (kEncThreads * kEncVec))). Thread handles
-// columns [h, h + 16) of row i.
+constexpr int kEncPerBlock = kEncThreads * kEncVec;  // K entries per workgroup of encode_a
+
+// Workgroup (i, by) of encode_a: row i, columns [h, h + 16) per thread with
+// h = (by * kEncThreads + thread) * 16. p2: LDS table (kBig only).
 template <bool kBig, bool kFold>
-__global__ __launch_bounds__(kEncThreads) void encode_a_kernel(ModConsts mc, int64_t m, int64_t k,
-                                                               const double* A, int64_t lda,
-                                                               const int32_t* shift_a,
-                                                               const int32_t* fold,
-                                                               int64_t m_pad, int64_t k_pad,
-                                                               int8_t* planes) {
-    __shared__ uint8_t p2[kBig ? kMaxModuli * kMaxShift : 1];
+__device__ __forceinline__ void encode_a_body(const ModConsts& mc, int64_t m, int64_t k,
+                                              const double* A, int64_t lda,
+                                              const int32_t* shift_a, const int32_t* fold,
+                                              int64_t m_pad, int64_t k_pad, int8_t* planes,
+                                              int64_t i, int64_t by, uint8_t* p2) {
     fill_p2<kBig>(mc, p2);
-    const int64_t i = blockIdx.x;
-    const int64_t h = ((int64_t)blockIdx.y * kEncThreads + threadIdx.x) * kEncVec;
+    const int64_t h = (by * kEncThreads + threadIdx.x) * kEncVec;
     if (h >= k_pad) return;
     Entry ent[kEncVec];
     const int32_t s = (i < m) ? shift_a[i] : 0;
@@ -147,7 +146,20 @@ __global__ __launch_bounds__(kEncThreads) void encode_a_kernel(ModConsts mc, int
     }
 }
 
-// grid: (n_pad / 64, k_pad / 64). A 64 (k) x 64 (n) tile of B: thread t
+// grid: (m_pad, ceil(k_pad / kEncPerBlock)).
+template <bool kBig, bool kFold>
+__global__ __launch_bounds__(kEncThreads) void encode_a_kernel(ModConsts mc, int64_t m, int64_t k,
+                                                               const double* A, int64_t lda,
+                                                               const int32_t* shift_a,
+                                                               const int32_t* fold,
+                                                               int64_t m_pad, int64_t k_pad,
+                                                               int8_t* planes) {
+    __shared__ uint8_t p2[kBig ? kMaxModuli * kMaxShift : 1];
+    encode_a_body<kBig, kFold>(mc, m, k, A, lda, shift_a, fold, m_pad, k_pad, planes, blockIdx.x,
+                               blockIdx.y, p2);
+}
+
+// Workgroup (bx, by) of encode_b: a 64 (k) x 64 (n) tile of B. Thread t
 // reads column j = t % 64 at rows 16 * (t / 64) .. + 15 (coalesced along j),
 // builds the 16 residues of that column segment per modulus, stores them as
 // one 16-byte word into LDS row j, and the tile is written out row by row
@@ -156,17 +168,14 @@ constexpr int kTB = 64;
 constexpr int kLdsRow = kTB + 16;  // bytes; padding spreads rows over banks
 
 template <bool kBig, bool kFold>
-__global__ __launch_bounds__(kEncThreads) void encode_b_kernel(ModConsts mc, int64_t k, int64_t n,
-                                                               const double* B, int64_t ldb,
-                                                               const int32_t* shift_b,
-                                                               const int32_t* fold,
-                                                               int64_t n_pad, int64_t k_pad,
-                                                               int8_t* planes) {
-    __shared__ __align__(16) int8_t tile[kTB * kLdsRow];
-    __shared__ uint8_t p2[kBig ? kMaxModuli * kMaxShift : 1];
+__device__ __forceinline__ void encode_b_body(const ModConsts& mc, int64_t k, int64_t n,
+                                              const double* B, int64_t ldb,
+                                              const int32_t* shift_b, const int32_t* fold,
+                                              int64_t n_pad, int64_t k_pad, int8_t* planes,
+                                              int64_t bx, int64_t by, int8_t* tile, uint8_t* p2) {
     fill_p2<kBig>(mc, p2);
-    const int64_t j0 = (int64_t)blockIdx.x * kTB;
-    const int64_t h0 = (int64_t)blockIdx.y * kTB;
+    const int64_t j0 = bx * kTB;
+    const int64_t h0 = by * kTB;
     const int tj = threadIdx.x & 63;
     const int hq = threadIdx.x >> 6;  // 0..3
     const int64_t j = j0 + tj;
@@ -200,14 +209,72 @@ __global__ __launch_bounds__(kEncThreads) void encode_b_kernel(ModConsts mc, int
     }
 }
 
+// grid: (n_pad / 64, k_pad / 64).
+template <bool kBig, bool kFold>
+__global__ __launch_bounds__(kEncThreads) void encode_b_kernel(ModConsts mc, int64_t k, int64_t n,
+                                                               const double* B, int64_t ldb,
+                                                               const int32_t* shift_b,
+                                                               const int32_t* fold,
+                                                               int64_t n_pad, int64_t k_pad,
+                                                               int8_t* planes) {
+    __shared__ __align__(16) int8_t tile[kTB * kLdsRow];
+    __shared__ uint8_t p2[kBig ? kMaxModuli * kMaxShift : 1];
+    encode_b_body<kBig, kFold>(mc, k, n, B, ldb, shift_b, fold, n_pad, k_pad, planes, blockIdx.x,
+                               blockIdx.y, tile, p2);
+}
+
+// ---- Grouped Reduce ----
+
+__global__ __launch_bounds__(kEncThreads) void group_encode_a_kernel(GroupArgs g) {
+    __shared__ uint8_t p2[kMaxModuli * kMaxShift];
+    const int32_t* pre = g.prefix + kGEncA * (g.count + 1);
+    const int p = group_find(pre, g.count, blockIdx.x);
+    const GProblem& P = g.probs[p];
+    const ModConsts& mc = g.mods[P.plan];
+    const int64_t lb = blockIdx.x - pre[p];
+    const int64_t per_row = (P.k_pad + kEncPerBlock - 1) / kEncPerBlock;
+    const int32_t* sa = reinterpret_cast<const int32_t*>(g.ws + P.off_sa);
+    int8_t* planes = reinterpret_cast<int8_t*>(g.ws + P.off_pa);
+    if (P.big)
+        encode_a_body<true, false>(mc, P.m, P.k, P.A, P.lda, sa, nullptr, P.m_pad, P.k_pad, planes,
+                                   lb / per_row, lb % per_row, p2);
+    else
+        encode_a_body<false, false>(mc, P.m, P.k, P.A, P.lda, sa, nullptr, P.m_pad, P.k_pad, planes,
+                                    lb / per_row, lb % per_row, p2);
+}
+
+__global__ __launch_bounds__(kEncThreads) void group_encode_b_kernel(GroupArgs g) {
+    __shared__ __align__(16) int8_t tile[kTB * kLdsRow];
+    __shared__ uint8_t p2[kMaxModuli * kMaxShift];
+    const int32_t* pre = g.prefix + kGEncB * (g.count + 1);
+    const int p = group_find(pre, g.count, blockIdx.x);
+    const GProblem& P = g.probs[p];
+    const ModConsts& mc = g.mods[P.plan];
+    const int64_t lb = blockIdx.x - pre[p];
+    const int64_t gx = P.n_pad / kTB;
+    const int32_t* sb = reinterpret_cast<const int32_t*>(g.ws + P.off_sb);
+    int8_t* planes = reinterpret_cast<int8_t*>(g.ws + P.off_pb);
+    if (P.big)
+        encode_b_body<true, false>(mc, P.k, P.n, P.B, P.ldb, sb, nullptr, P.n_pad, P.k_pad, planes,
+                                   lb % gx, lb / gx, tile, p2);
+    else
+        encode_b_body<false, false>(mc, P.k, P.n, P.B, P.ldb, sb, nullptr, P.n_pad, P.k_pad, planes,
+                                    lb % gx, lb / gx, tile, p2);
+}
+
 }  // namespace
+
+hipError_t launch_group_encode(hipStream_t st, const GroupArgs& g, int32_t enc_a, int32_t enc_b) {
+    if (enc_a > 0) group_encode_a_kernel<<<dim3((unsigned)enc_a), dim3(kEncThreads), 0, st>>>(g);
+    if (enc_b > 0) group_encode_b_kernel<<<dim3((unsigned)enc_b), dim3(kEncThreads), 0, st>>>(g);
+    return hipGetLastError();
+}
 
 hipError_t launch_encode_a(hipStream_t st, const ModConsts& mc, int64_t m, int64_t k,
                            const double* A, int64_t lda, const int32_t* shift_a, int64_t m_pad,
                            int64_t k_pad, int8_t* planes_a, bool big, const int32_t* fold) {
     if (m_pad <= 0 || k_pad <= 0) return hipSuccess;
-    const int64_t per_block = (int64_t)kEncThreads * kEncVec;
-    dim3 grid((unsigned)m_pad, (unsigned)((k_pad + per_block - 1) / per_block));
+    dim3 grid((unsigned)m_pad, (unsigned)((k_pad + kEncPerBlock - 1) / kEncPerBlock));
     auto go = [&](auto kernel) {
         kernel<<<grid, dim3(kEncThreads), 0, st>>>(mc, m, k, A, lda, shift_a, fold, m_pad, k_pad,
                                                    planes_a);

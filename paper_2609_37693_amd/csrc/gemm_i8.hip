@@ -40,6 +40,17 @@ constexpr int kOutRow = 264;
 
 enum class Epi { kMod, kMax };
 
+// Band order inside one modulus: bands of kGroup tile rows, column by
+// column, so consecutive tiles share operand strips.
+__device__ __forceinline__ void band_tile(int64_t t, int tiles_m, int tiles_n, int& tm, int& tn) {
+    const int64_t in_group = (int64_t)kGroup * tiles_n;
+    const int first_m = (int)(t / in_group) * kGroup;
+    const int gsize = min(tiles_m - first_m, kGroup);
+    const int64_t r = t % in_group;
+    tm = first_m + (int)(r % gsize);
+    tn = (int)(r / gsize);
+}
+
 // Tile order: all XCDs on one modulus at a time (the hardware dispatches
 // workgroup b to XCD b % 8), each XCD on a contiguous band-ordered eighth of
 // that modulus's tiles, so operand strips are shared inside one L2.
@@ -55,12 +66,7 @@ __device__ __forceinline__ void tile_of(int64_t bid, int tiles_m, int tiles_n, i
         l = (int)(bid / T);
         t = bid % T;
     }
-    const int64_t in_group = (int64_t)kGroup * tiles_n;
-    const int first_m = (int)(t / in_group) * kGroup;
-    const int gsize = min(tiles_m - first_m, kGroup);
-    const int64_t r = t % in_group;
-    tm = first_m + (int)(r % gsize);
-    tn = (int)(r / gsize);
+    band_tile(t, tiles_m, tiles_n, tm, tn);
 }
 
 // K pipeline: K steps of 64 bytes in four LDS stages, filled by
@@ -93,27 +99,24 @@ __device__ __forceinline__ void barrier_no_fence() {
     __builtin_amdgcn_sched_barrier(0);
 }
 
+// One 256 x 256 output tile (tm, tn) over K = k_pad (a positive multiple of
+// 64): gA and gB point at the first block of the tile's row strip in the A
+// and B planes of one modulus (plane_offset order), gZ at the tile's first
+// residue (row stride n_pad). Modulus m with Barrett constant mu (kMod);
+// row/column maxima into gmax_a/gmax_b (kMax). `lds` holds
+// kDStages * kDStage bytes; the caller synchronizes before reusing it.
 template <Epi E>
-__global__ __launch_bounds__(kThreads) void residue_gemm_kernel(ModConsts mc, int tiles_m, int tiles_n,
-                                                             int64_t k_pad, int64_t plane_a,
-                                                             int64_t plane_b, int64_t plane_z,
-                                                             int64_t n_pad,
-                                                             const int8_t* __restrict__ RA,
-                                                             const int8_t* __restrict__ RB,
-                                                             uint8_t* __restrict__ Z,
-                                                             int32_t* __restrict__ gmax_a,
-                                                             int32_t* __restrict__ gmax_b) {
-    __shared__ __align__(1024) int8_t lds[kDStages * kDStage];
-    int l, tm, tn;
-    tile_of(blockIdx.x, tiles_m, tiles_n, l, tm, tn);
+__device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad, int64_t n_pad,
+                                          const int8_t* __restrict__ gA,
+                                          const int8_t* __restrict__ gB, uint8_t* __restrict__ gZ,
+                                          int32_t* __restrict__ gmax_a,
+                                          int32_t* __restrict__ gmax_b, int tm, int tn,
+                                          int8_t* lds) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wi = wave >> 1;
     const int wj = wave & 1;
-    // first block of this tile's row strip in each plane (plane_offset)
-    const int8_t* gA = RA + (int64_t)l * plane_a + (int64_t)tm * kBM * k_pad;
-    const int8_t* gB = RB + (int64_t)l * plane_b + (int64_t)tn * kBN * k_pad;
 
     // Loads: wave-load R = wave * 8 + p copies kilobyte R % 16 of operand
     // R / 16's block for the step; lane L moves bytes [16 L, 16 L + 16).
@@ -229,7 +232,6 @@ __global__ __launch_bounds__(kThreads) void residue_gemm_kernel(ModConsts mc, in
     const int li = lane & 31;
     const int lj = (lane >> 5) * 4;
     if constexpr (E == Epi::kMod) {
-        const uint32_t m = mc.m[l], mu = mc.mu[l];
         uint8_t* sO = reinterpret_cast<uint8_t*>(lds);
 #pragma unroll
         for (int a = 0; a < kFM; ++a) {
@@ -253,7 +255,6 @@ __global__ __launch_bounds__(kThreads) void residue_gemm_kernel(ModConsts mc, in
             }
         }
         __syncthreads();
-        uint8_t* gZ = Z + (int64_t)l * plane_z + (int64_t)tm * kBM * n_pad + (int64_t)tn * kBN;
 #pragma unroll 4
         for (int c = tid; c < kBM * (kBN / 8); c += kThreads) {
             const int row = c / (kBN / 8), col = (c % (kBN / 8)) * 8;
@@ -289,7 +290,71 @@ __global__ __launch_bounds__(kThreads) void residue_gemm_kernel(ModConsts mc, in
     }
 }
 
+template <Epi E>
+__global__ __launch_bounds__(kThreads) void residue_gemm_kernel(ModConsts mc, int tiles_m, int tiles_n,
+                                                             int64_t k_pad, int64_t plane_a,
+                                                             int64_t plane_b, int64_t plane_z,
+                                                             int64_t n_pad,
+                                                             const int8_t* __restrict__ RA,
+                                                             const int8_t* __restrict__ RB,
+                                                             uint8_t* __restrict__ Z,
+                                                             int32_t* __restrict__ gmax_a,
+                                                             int32_t* __restrict__ gmax_b) {
+    __shared__ __align__(1024) int8_t lds[kDStages * kDStage];
+    int l, tm, tn;
+    tile_of(blockIdx.x, tiles_m, tiles_n, l, tm, tn);
+    const int8_t* gA = RA + (int64_t)l * plane_a + (int64_t)tm * kBM * k_pad;
+    const int8_t* gB = RB + (int64_t)l * plane_b + (int64_t)tn * kBN * k_pad;
+    uint8_t* gZ = (E == Epi::kMod)
+                      ? Z + (int64_t)l * plane_z + (int64_t)tm * kBM * n_pad + (int64_t)tn * kBN
+                      : nullptr;
+    gemm_tile<E>(E == Epi::kMod ? mc.m[l] : 0u, E == Epi::kMod ? mc.mu[l] : 0u, k_pad, n_pad, gA,
+                 gB, gZ, gmax_a, gmax_b, tm, tn, lds);
+}
+
+// Grouped residue GEMM, persistent: each workgroup takes work items
+// (problem, modulus, tile) from a global counter until the list is
+// exhausted; every wave of the workgroup sees the same item and leaves the
+// loop together. Items follow the problems in `order` (descending K), tiles
+// of one modulus in band order.
+__global__ __launch_bounds__(kThreads) void group_gemm_kernel(GroupArgs g, int32_t total) {
+    __shared__ __align__(1024) int8_t lds[kDStages * kDStage];
+    __shared__ int32_t next;
+    const int32_t* pre = g.prefix + kGTiles * (g.count + 1);
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(g.counter, 1);
+        __syncthreads();
+        const int32_t w = __builtin_amdgcn_readfirstlane(next);
+        __syncthreads();
+        if (w >= total) break;
+        const int q = group_find(pre, g.count, w);
+        const GProblem& P = g.probs[g.order[q]];
+        const int tiles_m = (int)(P.m_pad / kBM), tiles_n = (int)(P.n_pad / kBN);
+        const int64_t T = (int64_t)tiles_m * tiles_n;
+        const int64_t local = w - pre[q];
+        const int l = (int)(local / T);
+        int tm, tn;
+        band_tile(local % T, tiles_m, tiles_n, tm, tn);
+        const ModConsts& mc = g.mods[P.plan];
+        const int8_t* gA = reinterpret_cast<const int8_t*>(g.ws + P.off_pa) +
+                           (int64_t)l * P.m_pad * P.k_pad + (int64_t)tm * kBM * P.k_pad;
+        const int8_t* gB = reinterpret_cast<const int8_t*>(g.ws + P.off_pb) +
+                           (int64_t)l * P.n_pad * P.k_pad + (int64_t)tn * kBN * P.k_pad;
+        uint8_t* gZ = reinterpret_cast<uint8_t*>(g.ws + P.off_z) + (int64_t)l * P.m_pad * P.n_pad +
+                      (int64_t)tm * kBM * P.n_pad + (int64_t)tn * kBN;
+        gemm_tile<Epi::kMod>(mc.m[l], mc.mu[l], P.k_pad, P.n_pad, gA, gB, gZ, nullptr, nullptr, tm,
+                             tn, lds);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_group_gemm(hipStream_t st, const GroupArgs& g, int32_t tiles, int32_t workers) {
+    if (tiles <= 0) return hipSuccess;
+    const int32_t grid = workers < tiles ? workers : tiles;
+    group_gemm_kernel<<<dim3((unsigned)grid), dim3(kThreads), 0, st>>>(g, tiles);
+    return hipGetLastError();
+}
 
 hipError_t launch_residue_gemm(hipStream_t st, const ModConsts& mc, int64_t m_pad, int64_t n_pad,
                                int64_t k_pad, const int8_t* planes_a, const int8_t* planes_b,

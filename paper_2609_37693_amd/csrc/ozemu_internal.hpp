@@ -201,6 +201,53 @@ __host__ __device__ __forceinline__ uint32_t trunc_residue(uint64_t mant, int sh
     return barrett32(r0 * pow2mod(sh, m, mu), m, mu);
 }
 
+// ---- Grouped launches: many independent products in one set of launches.
+// The work of each phase is a list of workgroups, problem after problem:
+// prefix[kind * (count + 1) + p] is the first workgroup of problem p and
+// prefix[kind * (count + 1) + count] the total. The GEMM's work items
+// (modulus, tile) follow the problems in `order` (descending K), so the
+// longest tiles are taken first by the persistent workgroups.
+constexpr int kMaxGroup = 4096;  // problems per group (two 64-wide ballots)
+enum GKind : int { kGColInit = 0, kGRows, kGCols, kGShifts, kGEncA, kGEncB, kGTiles, kGCrt, kGKinds };
+
+struct GProblem {
+    int64_t m, n, k, m_pad, n_pad, k_pad;
+    const double* A;
+    const double* B;
+    double* C;
+    int64_t lda, ldb, ldc;
+    int64_t off_sa, off_sb, off_pa, off_pb, off_z;  // byte offsets into the workspace
+    int32_t plan, beta_a, beta_b, big;
+};
+
+// Kernel argument of every grouped launch (tables live in the workspace).
+struct GroupArgs {
+    const GProblem* probs;
+    const ModConsts* mods;
+    const CrtConsts* crts;
+    const int32_t* prefix;  // [kGKinds][count + 1]
+    const int32_t* order;   // problems in GEMM work order
+    char* ws;
+    int32_t* counter;       // persistent GEMM work counter
+    int32_t count;
+};
+
+#if defined(__HIPCC__)
+// Problem p with prefix[p] <= b < prefix[p + 1] (empty problems skipped);
+// the whole wave must be active. Two ballots: over every stride-th entry,
+// then inside the chosen stride (count <= 64 * 64).
+__device__ __forceinline__ int group_find(const int32_t* prefix, int count, int32_t b) {
+    const int lane = threadIdx.x & 63;
+    const int stride = (count + 63) >> 6;
+    const int i1 = lane * stride;
+    const unsigned long long m1 = __ballot(i1 < count && prefix[i1] <= b);
+    const int base = (63 - __clzll((long long)m1)) * stride;
+    const int i2 = base + lane;
+    const unsigned long long m2 = __ballot(lane < stride && i2 < count && prefix[i2] <= b);
+    return __builtin_amdgcn_readfirstlane(base + 63 - __clzll((long long)m2));
+}
+#endif
+
 // Launchers (defined in the .hip files). All take the caller's stream and
 // return hipSuccess or the launch error.
 // Row / column keys. A non-null `fold` (k entries) counts entry (i, h) of
@@ -251,5 +298,13 @@ hipError_t launch_reconstruct(hipStream_t st, const CrtConsts& cc, int64_t m, in
                               const int32_t* shift_a, const int32_t* shift_b, double* C,
                               int64_t ldc);
 hipError_t launch_zero_c(hipStream_t st, int64_t m, int64_t n, double* C, int64_t ldc);
+
+// Grouped phases; `total` is the phase's workgroup count (prefix total).
+hipError_t launch_group_init(hipStream_t st, const GroupArgs& g, int32_t total);
+hipError_t launch_group_scale(hipStream_t st, const GroupArgs& g, int32_t rows, int32_t cols,
+                              int32_t shifts);
+hipError_t launch_group_encode(hipStream_t st, const GroupArgs& g, int32_t enc_a, int32_t enc_b);
+hipError_t launch_group_gemm(hipStream_t st, const GroupArgs& g, int32_t tiles, int32_t workers);
+hipError_t launch_group_reconstruct(hipStream_t st, const GroupArgs& g, int32_t blocks, int dmax);
 
 }  // namespace ozemu

@@ -33,15 +33,12 @@ __device__ __forceinline__ int32_t folded_key(double x, const int32_t* fold, int
     }
 }
 
-// One workgroup per row; each thread strides the row with 16-byte loads.
-// With kFold, entry h counts as A_ih * 2^-fold[h] (a power-of-two column
-// scaling applied without rounding).
+// Key of one row, computed by a whole workgroup; each thread strides the
+// row with 16-byte loads. With kFold, entry h counts as A_ih * 2^-fold[h]
+// (a power-of-two column scaling applied without rounding).
 template <bool kFold>
-__global__ __launch_bounds__(kScaleThreads) void scale_rows_kernel(int64_t k, const double* A,
-                                                                   int64_t lda, const int32_t* fold,
-                                                                   int32_t* key_a) {
-    const int64_t i = blockIdx.x;
-    const double* row = A + i * lda;
+__device__ __forceinline__ void scale_row_body(int64_t k, const double* row, const int32_t* fold,
+                                               int32_t* key_out) {
     int32_t key = kKeyZero;
     const bool vec = ((reinterpret_cast<uintptr_t>(row) & 15) == 0);
     if (vec) {
@@ -64,26 +61,44 @@ __global__ __launch_bounds__(kScaleThreads) void scale_rows_kernel(int64_t k, co
     if (threadIdx.x == 0) {
         int32_t r = part[0];
         for (int w = 1; w < kScaleThreads / 64; ++w) r = max(r, part[w]);
-        key_a[i] = r;
+        *key_out = r;
     }
+}
+
+// One workgroup per row.
+template <bool kFold>
+__global__ __launch_bounds__(kScaleThreads) void scale_rows_kernel(int64_t k, const double* A,
+                                                                   int64_t lda, const int32_t* fold,
+                                                                   int32_t* key_a) {
+    const int64_t i = blockIdx.x;
+    scale_row_body<kFold>(k, A + i * lda, fold, key_a + i);
 }
 
 constexpr int kColRows = 64;  // rows of B per workgroup slab
 
-// grid: (ceil(n / 256), ceil(k / kColRows)); key_b pre-filled with kKeyZero.
-// With kFold, entry (h, j) counts as B_hj * 2^-fold[h].
+// Workgroup (bx, by) of the column scan: columns 256 bx .. + 255 over rows
+// kColRows by .. + kColRows - 1; key_b pre-filled with kKeyZero. With
+// kFold, entry (h, j) counts as B_hj * 2^-fold[h].
+template <bool kFold>
+__device__ __forceinline__ void scale_cols_body(int64_t k, int64_t n, const double* B, int64_t ldb,
+                                                const int32_t* fold, int32_t* key_b, int64_t bx,
+                                                int64_t by) {
+    const int64_t j = bx * kScaleThreads + threadIdx.x;
+    if (j >= n) return;
+    const int64_t h0 = by * kColRows;
+    const int64_t h1 = min(k, h0 + kColRows);
+    int32_t key = kKeyZero;
+    for (int64_t h = h0; h < h1; ++h) key = max(key, folded_key<kFold>(B[h * ldb + j], fold, h));
+    if (key != kKeyZero) atomicMax(key_b + j, key);
+}
+
+// grid: (ceil(n / 256), ceil(k / kColRows)).
 template <bool kFold>
 __global__ __launch_bounds__(kScaleThreads) void scale_cols_kernel(int64_t k, int64_t n,
                                                                    const double* B, int64_t ldb,
                                                                    const int32_t* fold,
                                                                    int32_t* key_b) {
-    const int64_t j = (int64_t)blockIdx.x * kScaleThreads + threadIdx.x;
-    if (j >= n) return;
-    const int64_t h0 = (int64_t)blockIdx.y * kColRows;
-    const int64_t h1 = min(k, h0 + kColRows);
-    int32_t key = kKeyZero;
-    for (int64_t h = h0; h < h1; ++h) key = max(key, folded_key<kFold>(B[h * ldb + j], fold, h));
-    if (key != kKeyZero) atomicMax(key_b + j, key);
+    scale_cols_body<kFold>(k, n, B, ldb, fold, key_b, blockIdx.x, blockIdx.y);
 }
 
 __global__ void fill_i32_kernel(int64_t count, int32_t value, int32_t* out) {
@@ -92,21 +107,19 @@ __global__ void fill_i32_kernel(int64_t count, int32_t value, int32_t* out) {
 }
 
 // shift = beta - e for a nonzero row, 0 for a zero row, the non-finite
-// marker otherwise; beta is per entry when beta_per_entry is given.
+// marker otherwise.
+__device__ __forceinline__ int32_t key_to_shift(int32_t key, int32_t beta) {
+    if (key == kKeyNonFinite) return kShiftNonFinite;
+    if (key == kKeyZero) return 0;
+    return beta - key;
+}
+
+// beta is per entry when beta_per_entry is given.
 __global__ void keys_to_shifts_kernel(int64_t count, int32_t* io, int beta,
                                       const int32_t* beta_per_entry) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    int32_t key = io[i];
-    int32_t b = beta_per_entry ? beta_per_entry[i] : beta;
-    int32_t s;
-    if (key == kKeyNonFinite)
-        s = kShiftNonFinite;
-    else if (key == kKeyZero)
-        s = 0;
-    else
-        s = b - key;
-    io[i] = s;
+    io[i] = key_to_shift(io[i], beta_per_entry ? beta_per_entry[i] : beta);
 }
 
 // Bound-adaptive mode: abar = ceil(|x| 2^(6 - e)) in [0, 64]. The scaling
@@ -179,7 +192,69 @@ __global__ void bound_shifts_kernel(int64_t count, const int32_t* key, const int
     shift[i] = s;
 }
 
+// ---- Grouped Scale ----
+
+// Column keys of every problem pre-filled with kKeyZero (256 per
+// workgroup); workgroup 0 also zeroes the GEMM work counter.
+__global__ __launch_bounds__(kScaleThreads) void group_init_kernel(GroupArgs g, int32_t total) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *g.counter = 0;
+    if ((int32_t)blockIdx.x >= total) return;
+    const int32_t* pre = g.prefix + kGColInit * (g.count + 1);
+    const int p = group_find(pre, g.count, blockIdx.x);
+    const GProblem& P = g.probs[p];
+    const int64_t j = (int64_t)(blockIdx.x - pre[p]) * kScaleThreads + threadIdx.x;
+    if (j < P.n) reinterpret_cast<int32_t*>(g.ws + P.off_sb)[j] = kKeyZero;
+}
+
+__global__ __launch_bounds__(kScaleThreads) void group_scale_rows_kernel(GroupArgs g) {
+    const int32_t* pre = g.prefix + kGRows * (g.count + 1);
+    const int p = group_find(pre, g.count, blockIdx.x);
+    const GProblem& P = g.probs[p];
+    const int64_t i = blockIdx.x - pre[p];
+    scale_row_body<false>(P.k, P.A + i * P.lda, nullptr,
+                          reinterpret_cast<int32_t*>(g.ws + P.off_sa) + i);
+}
+
+__global__ __launch_bounds__(kScaleThreads) void group_scale_cols_kernel(GroupArgs g) {
+    const int32_t* pre = g.prefix + kGCols * (g.count + 1);
+    const int p = group_find(pre, g.count, blockIdx.x);
+    const GProblem& P = g.probs[p];
+    const int64_t lb = blockIdx.x - pre[p];
+    const int64_t gx = (P.n + kScaleThreads - 1) / kScaleThreads;
+    scale_cols_body<false>(P.k, P.n, P.B, P.ldb, nullptr,
+                           reinterpret_cast<int32_t*>(g.ws + P.off_sb), lb % gx, lb / gx);
+}
+
+// Keys to shifts: thread t < m handles row t, then the n columns.
+__global__ __launch_bounds__(kScaleThreads) void group_shifts_kernel(GroupArgs g) {
+    const int32_t* pre = g.prefix + kGShifts * (g.count + 1);
+    const int p = group_find(pre, g.count, blockIdx.x);
+    const GProblem& P = g.probs[p];
+    const int64_t t = (int64_t)(blockIdx.x - pre[p]) * kScaleThreads + threadIdx.x;
+    if (t < P.m) {
+        int32_t* sa = reinterpret_cast<int32_t*>(g.ws + P.off_sa);
+        sa[t] = key_to_shift(sa[t], P.beta_a);
+    } else if (t < P.m + P.n) {
+        int32_t* sb = reinterpret_cast<int32_t*>(g.ws + P.off_sb);
+        sb[t - P.m] = key_to_shift(sb[t - P.m], P.beta_b);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_group_init(hipStream_t st, const GroupArgs& g, int32_t total) {
+    group_init_kernel<<<dim3((unsigned)(total > 0 ? total : 1)), dim3(kScaleThreads), 0, st>>>(g,
+                                                                                              total);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_scale(hipStream_t st, const GroupArgs& g, int32_t rows, int32_t cols,
+                              int32_t shifts) {
+    if (rows > 0) group_scale_rows_kernel<<<dim3((unsigned)rows), dim3(kScaleThreads), 0, st>>>(g);
+    if (cols > 0) group_scale_cols_kernel<<<dim3((unsigned)cols), dim3(kScaleThreads), 0, st>>>(g);
+    if (shifts > 0) group_shifts_kernel<<<dim3((unsigned)shifts), dim3(kScaleThreads), 0, st>>>(g);
+    return hipGetLastError();
+}
 
 hipError_t launch_scale_rows(hipStream_t st, int64_t m, int64_t k, const double* A, int64_t lda,
                              int32_t* key_a, const int32_t* fold) {

@@ -190,3 +190,44 @@ def test_backward_workspace_covers_both_products():
     _lib.check(_lib.load().ozemu_bwd_workspace_size(plan.handle, m, n, k, C.byref(v)))
     # fresh dY planes, transposed cached planes, residues of the larger product
     assert v.value >= 14 * (mp * np_ + kp * max(mp, np_) + kp * max(mp, np_))
+
+
+def _group_create(count, plans, m, n, k, ptr=1, ld=None):
+    lib = _lib.load()
+    h = C.c_void_p()
+    I64 = C.c_int64 * max(count, 1)
+    VP = C.c_void_p * max(count, 1)
+    lds = ld if ld is not None else [max(a, b, c, 1) for a, b, c in zip(m, n, k)]
+    st = lib.ozemu_group_create(C.byref(h), count, VP(*[pl.handle.value for pl in plans]),
+                                I64(*m), I64(*n), I64(*k), VP(*([ptr] * count)), I64(*lds),
+                                VP(*([ptr] * count)), I64(*lds), VP(*([ptr] * count)), I64(*lds))
+    return st, h
+
+
+def test_group_host_side():
+    S = _lib
+    lib = _lib.load()
+    w = oz.Plan(num_moduli=14, scaling="W")
+    w20 = oz.Plan(num_moduli=20, scaling="W")
+    st, h = _group_create(3, [w, w20, w], [300, 0, 64], [200, 9, 64], [100, 9, 0])
+    assert st == S.OZEMU_OK
+    v = C.c_size_t()
+    _lib.check(lib.ozemu_group_workspace_size(h, C.byref(v)))
+    # tables, then shifts, 14 + 0 + 0 planes and residues of the one problem with work
+    assert v.value >= 14 * (512 * 128 + 256 * 128 + 512 * 256)
+    assert lib.ozemu_group_run(h, None, None, 0) == S.OZEMU_ERR_WORKSPACE
+    assert lib.ozemu_group_destroy(h) == S.OZEMU_OK
+    # an empty group is valid and its run is a no-op
+    st, h = _group_create(0, [], [], [], [])
+    assert st == S.OZEMU_OK
+    assert lib.ozemu_group_run(h, None, None, 0) == S.OZEMU_OK
+    lib.ozemu_group_destroy(h)
+    # per-problem validation names the problem
+    st, h = _group_create(2, [w, w], [8, 8], [8, 8], [8, 131072])
+    assert st == S.OZEMU_ERR_K_TOO_LARGE and "problem 1" in lib.ozemu_last_error().decode()
+    st, h = _group_create(2, [w, w], [8, 8], [8, 8], [8, 8], ptr=0)
+    assert st == S.OZEMU_ERR_INVALID_ARG
+    st, h = _group_create(1, [oz.Plan(num_moduli=16, scaling="G")], [8], [8], [8])
+    assert st == S.OZEMU_ERR_UNSUPPORTED
+    assert _group_create(4097, [w] * 4097, [1] * 4097, [1] * 4097, [1] * 4097)[0] == \
+        S.OZEMU_ERR_INVALID_ARG
