@@ -22,6 +22,7 @@ struct ozemu_plan_s {
 // prefixes, laid out as they are copied to the start of the workspace.
 struct ozemu_group_s {
     int count = 0, nplans = 0, dmax = 2;
+    bool big = false;  // some problem keeps more than 63 bits
     size_t table_bytes = 0, ws_bytes = 0;
     size_t off_probs = 0, off_mods = 0, off_crts = 0, off_prefix = 0, off_order = 0,
            off_counter = 0;
@@ -590,7 +591,7 @@ ozemu_status ozemu_group_create(ozemu_group* out, int count, const ozemu_plan* p
     g->off_order = off;
     off = align256(off + sizeof(int32_t) * (size_t)count);
     g->off_counter = off;
-    off = align256(off + sizeof(int32_t));
+    off = align256(off + sizeof(int32_t) * kXcds);
     g->table_bytes = off;
     // per-problem workspace regions and work prefixes
     std::vector<int32_t> prefix((size_t)kGKinds * (count + 1), 0);
@@ -620,22 +621,27 @@ ozemu_status ozemu_group_create(ozemu_group* out, int count, const ozemu_plan* p
             blocks[kGRows] = P.m;
             blocks[kGCols] = (int64_t)cdiv32(P.n, 256) * cdiv32(P.k, 64);
             blocks[kGShifts] = cdiv32(P.m + P.n, 256);
-            blocks[kGEncA] = P.m_pad * cdiv32(P.k_pad, 4096);
+            blocks[kGEncA] = cdiv32(P.m_pad * (P.k_pad / 16), 256);
             blocks[kGEncB] = (P.n_pad / 64) * (P.k_pad / 64);
         }
         if (active) blocks[kGCrt] = cdiv32(P.m * ((P.n + 3) / 4), 256);
-        for (int kind = 0; kind < kGKinds; ++kind) {
-            if (kind == kGTiles) continue;
+        for (int kind = 0; kind < kGTiles; ++kind) {
             prefix[(size_t)kind * (count + 1) + p] = (int32_t)tot[kind];
             tot[kind] += blocks[kind];
         }
+        if (work && P.big) g->big = true;
     }
+    // per-XCD GEMM work lists over the problems in descending-K order
     for (int q = 0; q < count; ++q) {
         const GProblem& P = probs[order[q]];
         const bool work = P.m > 0 && P.n > 0 && P.k > 0;
-        prefix[(size_t)kGTiles * (count + 1) + q] = (int32_t)tot[kGTiles];
-        if (work)
-            tot[kGTiles] += (int64_t)uniq[P.plan]->n * (P.m_pad / kTileM) * (P.n_pad / kTileN);
+        const int64_t T = (P.m_pad / kTileM) * (P.n_pad / kTileN);
+        for (int x = 0; x < kXcds; ++x) {
+            prefix[(size_t)(kGTiles + x) * (count + 1) + q] = (int32_t)tot[kGTiles + x];
+            int64_t lo, hi;
+            xcd_share(T, x, q, lo, hi);
+            if (work) tot[kGTiles + x] += (int64_t)uniq[P.plan]->n * (hi - lo);
+        }
     }
     for (int kind = 0; kind < kGKinds; ++kind) {
         if (tot[kind] > INT32_MAX) {
@@ -711,8 +717,9 @@ ozemu_status ozemu_group_run(ozemu_group group, void* stream, void* workspace, s
         workers = 256;
     ozemu_status s = hip_check(launch_group_init(st, a, T[kGColInit]), "group init");
     if (!s) s = hip_check(launch_group_scale(st, a, T[kGRows], T[kGCols], T[kGShifts]), "group scale");
-    if (!s) s = hip_check(launch_group_encode(st, a, T[kGEncA], T[kGEncB]), "group encode");
-    if (!s) s = hip_check(launch_group_gemm(st, a, T[kGTiles], workers), "group gemm");
+    if (!s)
+        s = hip_check(launch_group_encode(st, a, T[kGEncA], T[kGEncB], group->big), "group encode");
+    if (!s) s = hip_check(launch_group_gemm(st, a, T + kGTiles, workers), "group gemm");
     if (!s) s = hip_check(launch_group_reconstruct(st, a, T[kGCrt], group->dmax), "group reconstruct");
     return s;
 }

@@ -99,23 +99,36 @@ __device__ __forceinline__ void fill_p2(const ModConsts& mc, uint8_t* p2) {
     }
 }
 
-constexpr int kEncPerBlock = kEncThreads * kEncVec;  // K entries per workgroup of encode_a
+// encode_a works on 16-entry chunks of the plane's rows, k_pad / 16 per
+// row, 256 consecutive chunks per workgroup (crossing rows when k_pad is
+// short), so every thread has work for any K.
+constexpr int64_t kChunksPerBlock = kEncThreads;
 
-// Workgroup (i, by) of encode_a: row i, columns [h, h + 16) per thread with
-// h = (by * kEncThreads + thread) * 16. p2: LDS table (kBig only).
+// Chunk c of the A planes: row i = c / (k_pad / 16), columns [h, h + 16).
+// Padding rows and columns get zeros without residue work. p2: LDS table
+// (kBig only).
 template <bool kBig, bool kFold>
 __device__ __forceinline__ void encode_a_body(const ModConsts& mc, int64_t m, int64_t k,
                                               const double* A, int64_t lda,
                                               const int32_t* shift_a, const int32_t* fold,
                                               int64_t m_pad, int64_t k_pad, int8_t* planes,
-                                              int64_t i, int64_t by, uint8_t* p2) {
+                                              int64_t c, uint8_t* p2) {
     fill_p2<kBig>(mc, p2);
-    const int64_t h = (by * kEncThreads + threadIdx.x) * kEncVec;
-    if (h >= k_pad) return;
+    const int64_t cpr = k_pad / kEncVec;
+    const int64_t i = c / cpr;
+    const int64_t h = (c % cpr) * kEncVec;
+    if (i >= m_pad) return;
+    const int64_t plane_stride = m_pad * k_pad;
+    int8_t* out = planes + plane_offset(i, h, k_pad);
+    if (i >= m || h >= k) {
+        for (int l = 0; l < mc.n; ++l)
+            *reinterpret_cast<uint4*>(out + (int64_t)l * plane_stride) = make_uint4(0, 0, 0, 0);
+        return;
+    }
     Entry ent[kEncVec];
-    const int32_t s = (i < m) ? shift_a[i] : 0;
+    const int32_t s = shift_a[i];
     const double* row = A + i * lda;
-    if (i < m && h + kEncVec <= k && ((reinterpret_cast<uintptr_t>(row + h) & 15) == 0)) {
+    if (h + kEncVec <= k && ((reinterpret_cast<uintptr_t>(row + h) & 15) == 0)) {
         const double2* p2v = reinterpret_cast<const double2*>(row + h);
 #pragma unroll
         for (int q = 0; q < kEncVec / 2; ++q) {
@@ -126,13 +139,11 @@ __device__ __forceinline__ void encode_a_body(const ModConsts& mc, int64_t m, in
     } else {
 #pragma unroll
         for (int q = 0; q < kEncVec; ++q) {
-            const bool in = i < m && h + q < k;
+            const bool in = h + q < k;
             double v = in ? row[h + q] : 0.0;
             ent[q] = make_entry<kBig>(v, in ? entry_shift<kFold>(s, fold, h + q) : 0);
         }
     }
-    const int64_t plane_stride = m_pad * k_pad;
-    int8_t* out = planes + plane_offset(i, h, k_pad);
     for (int l = 0; l < mc.n; ++l) {
         int8_t r[kEncVec];
 #pragma unroll
@@ -146,7 +157,7 @@ __device__ __forceinline__ void encode_a_body(const ModConsts& mc, int64_t m, in
     }
 }
 
-// grid: (m_pad, ceil(k_pad / kEncPerBlock)).
+// grid: ceil(m_pad * k_pad / 16 / 256).
 template <bool kBig, bool kFold>
 __global__ __launch_bounds__(kEncThreads) void encode_a_kernel(ModConsts mc, int64_t m, int64_t k,
                                                                const double* A, int64_t lda,
@@ -155,8 +166,8 @@ __global__ __launch_bounds__(kEncThreads) void encode_a_kernel(ModConsts mc, int
                                                                int64_t m_pad, int64_t k_pad,
                                                                int8_t* planes) {
     __shared__ uint8_t p2[kBig ? kMaxModuli * kMaxShift : 1];
-    encode_a_body<kBig, kFold>(mc, m, k, A, lda, shift_a, fold, m_pad, k_pad, planes, blockIdx.x,
-                               blockIdx.y, p2);
+    encode_a_body<kBig, kFold>(mc, m, k, A, lda, shift_a, fold, m_pad, k_pad, planes,
+                               (int64_t)blockIdx.x * kChunksPerBlock + threadIdx.x, p2);
 }
 
 // Workgroup (bx, by) of encode_b: a 64 (k) x 64 (n) tile of B. Thread t
@@ -173,9 +184,19 @@ __device__ __forceinline__ void encode_b_body(const ModConsts& mc, int64_t k, in
                                               const int32_t* shift_b, const int32_t* fold,
                                               int64_t n_pad, int64_t k_pad, int8_t* planes,
                                               int64_t bx, int64_t by, int8_t* tile, uint8_t* p2) {
-    fill_p2<kBig>(mc, p2);
     const int64_t j0 = bx * kTB;
     const int64_t h0 = by * kTB;
+    const int64_t plane_stride = n_pad * k_pad;
+    const int orow = threadIdx.x >> 2;    // output column of B (row of the plane)
+    const int ochunk = threadIdx.x & 3;   // 16-byte chunk of K
+    if (j0 >= n || h0 >= k) {  // a tile of padding: zeros, no residue work
+        for (int l = 0; l < mc.n; ++l)
+            *reinterpret_cast<uint4*>(planes + (int64_t)l * plane_stride +
+                                      plane_offset(j0 + orow, h0 + ochunk * kEncVec, k_pad)) =
+                make_uint4(0, 0, 0, 0);
+        return;
+    }
+    fill_p2<kBig>(mc, p2);
     const int tj = threadIdx.x & 63;
     const int hq = threadIdx.x >> 6;  // 0..3
     const int64_t j = j0 + tj;
@@ -188,9 +209,6 @@ __device__ __forceinline__ void encode_b_body(const ModConsts& mc, int64_t k, in
         double v = in ? B[h * ldb + j] : 0.0;
         ent[q] = make_entry<kBig>(v, in ? entry_shift<kFold>(s, fold, h) : 0);
     }
-    const int64_t plane_stride = n_pad * k_pad;
-    const int orow = threadIdx.x >> 2;    // output column of B (row of the plane)
-    const int ochunk = threadIdx.x & 3;   // 16-byte chunk of K
     for (int l = 0; l < mc.n; ++l) {
         int8_t r[kEncVec];
 #pragma unroll
@@ -224,49 +242,52 @@ __global__ __launch_bounds__(kEncThreads) void encode_b_kernel(ModConsts mc, int
 }
 
 // ---- Grouped Reduce ----
+// kBig is chosen for the whole group (the form for kept bits above 63 is
+// exact for any shift, only slower).
 
+template <bool kBig>
 __global__ __launch_bounds__(kEncThreads) void group_encode_a_kernel(GroupArgs g) {
-    __shared__ uint8_t p2[kMaxModuli * kMaxShift];
+    __shared__ uint8_t p2[kBig ? kMaxModuli * kMaxShift : 1];
     const int32_t* pre = g.prefix + kGEncA * (g.count + 1);
     const int p = group_find(pre, g.count, blockIdx.x);
     const GProblem& P = g.probs[p];
-    const ModConsts& mc = g.mods[P.plan];
-    const int64_t lb = blockIdx.x - pre[p];
-    const int64_t per_row = (P.k_pad + kEncPerBlock - 1) / kEncPerBlock;
-    const int32_t* sa = reinterpret_cast<const int32_t*>(g.ws + P.off_sa);
-    int8_t* planes = reinterpret_cast<int8_t*>(g.ws + P.off_pa);
-    if (P.big)
-        encode_a_body<true, false>(mc, P.m, P.k, P.A, P.lda, sa, nullptr, P.m_pad, P.k_pad, planes,
-                                   lb / per_row, lb % per_row, p2);
-    else
-        encode_a_body<false, false>(mc, P.m, P.k, P.A, P.lda, sa, nullptr, P.m_pad, P.k_pad, planes,
-                                    lb / per_row, lb % per_row, p2);
+    encode_a_body<kBig, false>(g.mods[P.plan], P.m, P.k, P.A, P.lda,
+                               reinterpret_cast<const int32_t*>(g.ws + P.off_sa), nullptr, P.m_pad,
+                               P.k_pad, reinterpret_cast<int8_t*>(g.ws + P.off_pa),
+                               (int64_t)(blockIdx.x - pre[p]) * kChunksPerBlock + threadIdx.x, p2);
 }
 
+template <bool kBig>
 __global__ __launch_bounds__(kEncThreads) void group_encode_b_kernel(GroupArgs g) {
     __shared__ __align__(16) int8_t tile[kTB * kLdsRow];
-    __shared__ uint8_t p2[kMaxModuli * kMaxShift];
+    __shared__ uint8_t p2[kBig ? kMaxModuli * kMaxShift : 1];
     const int32_t* pre = g.prefix + kGEncB * (g.count + 1);
     const int p = group_find(pre, g.count, blockIdx.x);
     const GProblem& P = g.probs[p];
-    const ModConsts& mc = g.mods[P.plan];
     const int64_t lb = blockIdx.x - pre[p];
     const int64_t gx = P.n_pad / kTB;
-    const int32_t* sb = reinterpret_cast<const int32_t*>(g.ws + P.off_sb);
-    int8_t* planes = reinterpret_cast<int8_t*>(g.ws + P.off_pb);
-    if (P.big)
-        encode_b_body<true, false>(mc, P.k, P.n, P.B, P.ldb, sb, nullptr, P.n_pad, P.k_pad, planes,
-                                   lb % gx, lb / gx, tile, p2);
-    else
-        encode_b_body<false, false>(mc, P.k, P.n, P.B, P.ldb, sb, nullptr, P.n_pad, P.k_pad, planes,
-                                    lb % gx, lb / gx, tile, p2);
+    encode_b_body<kBig, false>(g.mods[P.plan], P.k, P.n, P.B, P.ldb,
+                               reinterpret_cast<const int32_t*>(g.ws + P.off_sb), nullptr, P.n_pad,
+                               P.k_pad, reinterpret_cast<int8_t*>(g.ws + P.off_pb), lb % gx, lb / gx,
+                               tile, p2);
 }
 
 }  // namespace
 
-hipError_t launch_group_encode(hipStream_t st, const GroupArgs& g, int32_t enc_a, int32_t enc_b) {
-    if (enc_a > 0) group_encode_a_kernel<<<dim3((unsigned)enc_a), dim3(kEncThreads), 0, st>>>(g);
-    if (enc_b > 0) group_encode_b_kernel<<<dim3((unsigned)enc_b), dim3(kEncThreads), 0, st>>>(g);
+hipError_t launch_group_encode(hipStream_t st, const GroupArgs& g, int32_t enc_a, int32_t enc_b,
+                               bool big) {
+    if (enc_a > 0) {
+        if (big)
+            group_encode_a_kernel<true><<<dim3((unsigned)enc_a), dim3(kEncThreads), 0, st>>>(g);
+        else
+            group_encode_a_kernel<false><<<dim3((unsigned)enc_a), dim3(kEncThreads), 0, st>>>(g);
+    }
+    if (enc_b > 0) {
+        if (big)
+            group_encode_b_kernel<true><<<dim3((unsigned)enc_b), dim3(kEncThreads), 0, st>>>(g);
+        else
+            group_encode_b_kernel<false><<<dim3((unsigned)enc_b), dim3(kEncThreads), 0, st>>>(g);
+    }
     return hipGetLastError();
 }
 
@@ -274,7 +295,7 @@ hipError_t launch_encode_a(hipStream_t st, const ModConsts& mc, int64_t m, int64
                            const double* A, int64_t lda, const int32_t* shift_a, int64_t m_pad,
                            int64_t k_pad, int8_t* planes_a, bool big, const int32_t* fold) {
     if (m_pad <= 0 || k_pad <= 0) return hipSuccess;
-    dim3 grid((unsigned)m_pad, (unsigned)((k_pad + kEncPerBlock - 1) / kEncPerBlock));
+    dim3 grid((unsigned)((m_pad * (k_pad / kEncVec) + kChunksPerBlock - 1) / kChunksPerBlock));
     auto go = [&](auto kernel) {
         kernel<<<grid, dim3(kEncThreads), 0, st>>>(mc, m, k, A, lda, shift_a, fold, m_pad, k_pad,
                                                    planes_a);

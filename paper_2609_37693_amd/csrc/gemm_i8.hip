@@ -312,47 +312,57 @@ __global__ __launch_bounds__(kThreads) void residue_gemm_kernel(ModConsts mc, in
                  gB, gZ, gmax_a, gmax_b, tm, tn, lds);
 }
 
-// Grouped residue GEMM, persistent: each workgroup takes work items
-// (problem, modulus, tile) from a global counter until the list is
-// exhausted; every wave of the workgroup sees the same item and leaves the
-// loop together. Items follow the problems in `order` (descending K), tiles
-// of one modulus in band order.
-__global__ __launch_bounds__(kThreads) void group_gemm_kernel(GroupArgs g, int32_t total) {
+// Grouped residue GEMM, persistent: workgroup b starts on the list of its
+// XCD (b % 8, the hardware's round-robin placement) and takes work items
+// (problem, modulus, tile) from that list's counter; when it is exhausted
+// it helps the other XCDs' lists in turn. Every wave of a workgroup sees the
+// same item, so all waves leave the loops together.
+__global__ __launch_bounds__(kThreads) void group_gemm_kernel(GroupArgs g) {
     __shared__ __align__(1024) int8_t lds[kDStages * kDStage];
     __shared__ int32_t next;
-    const int32_t* pre = g.prefix + kGTiles * (g.count + 1);
-    for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(g.counter, 1);
-        __syncthreads();
-        const int32_t w = __builtin_amdgcn_readfirstlane(next);
-        __syncthreads();
-        if (w >= total) break;
-        const int q = group_find(pre, g.count, w);
-        const GProblem& P = g.probs[g.order[q]];
-        const int tiles_m = (int)(P.m_pad / kBM), tiles_n = (int)(P.n_pad / kBN);
-        const int64_t T = (int64_t)tiles_m * tiles_n;
-        const int64_t local = w - pre[q];
-        const int l = (int)(local / T);
-        int tm, tn;
-        band_tile(local % T, tiles_m, tiles_n, tm, tn);
-        const ModConsts& mc = g.mods[P.plan];
-        const int8_t* gA = reinterpret_cast<const int8_t*>(g.ws + P.off_pa) +
-                           (int64_t)l * P.m_pad * P.k_pad + (int64_t)tm * kBM * P.k_pad;
-        const int8_t* gB = reinterpret_cast<const int8_t*>(g.ws + P.off_pb) +
-                           (int64_t)l * P.n_pad * P.k_pad + (int64_t)tn * kBN * P.k_pad;
-        uint8_t* gZ = reinterpret_cast<uint8_t*>(g.ws + P.off_z) + (int64_t)l * P.m_pad * P.n_pad +
-                      (int64_t)tm * kBM * P.n_pad + (int64_t)tn * kBN;
-        gemm_tile<Epi::kMod>(mc.m[l], mc.mu[l], P.k_pad, P.n_pad, gA, gB, gZ, nullptr, nullptr, tm,
-                             tn, lds);
+    const int x0 = blockIdx.x & (kXcds - 1);
+    for (int d = 0; d < kXcds; ++d) {
+        const int x = (x0 + d) & (kXcds - 1);
+        const int32_t* pre = g.prefix + (kGTiles + x) * (g.count + 1);
+        const int32_t total = pre[g.count];
+        for (;;) {
+            if (threadIdx.x == 0) next = atomicAdd(g.counter + x, 1);
+            __syncthreads();
+            const int32_t w = __builtin_amdgcn_readfirstlane(next);
+            __syncthreads();
+            if (w >= total) break;
+            const int q = group_find(pre, g.count, w);
+            const GProblem& P = g.probs[g.order[q]];
+            const int tiles_m = (int)(P.m_pad / kBM), tiles_n = (int)(P.n_pad / kBN);
+            int64_t lo, hi;
+            xcd_share((int64_t)tiles_m * tiles_n, x, q, lo, hi);
+            const int64_t local = w - pre[q];
+            const int l = (int)(local / (hi - lo));
+            int tm, tn;
+            band_tile(lo + local % (hi - lo), tiles_m, tiles_n, tm, tn);
+            const ModConsts& mc = g.mods[P.plan];
+            const int8_t* gA = reinterpret_cast<const int8_t*>(g.ws + P.off_pa) +
+                               (int64_t)l * P.m_pad * P.k_pad + (int64_t)tm * kBM * P.k_pad;
+            const int8_t* gB = reinterpret_cast<const int8_t*>(g.ws + P.off_pb) +
+                               (int64_t)l * P.n_pad * P.k_pad + (int64_t)tn * kBN * P.k_pad;
+            uint8_t* gZ = reinterpret_cast<uint8_t*>(g.ws + P.off_z) +
+                          (int64_t)l * P.m_pad * P.n_pad + (int64_t)tm * kBM * P.n_pad +
+                          (int64_t)tn * kBN;
+            gemm_tile<Epi::kMod>(mc.m[l], mc.mu[l], P.k_pad, P.n_pad, gA, gB, gZ, nullptr, nullptr,
+                                 tm, tn, lds);
+        }
     }
 }
 
 }  // namespace
 
-hipError_t launch_group_gemm(hipStream_t st, const GroupArgs& g, int32_t tiles, int32_t workers) {
+hipError_t launch_group_gemm(hipStream_t st, const GroupArgs& g, const int32_t* tiles_per_xcd,
+                             int32_t workers) {
+    int64_t tiles = 0;
+    for (int x = 0; x < kXcds; ++x) tiles += tiles_per_xcd[x];
     if (tiles <= 0) return hipSuccess;
-    const int32_t grid = workers < tiles ? workers : tiles;
-    group_gemm_kernel<<<dim3((unsigned)grid), dim3(kThreads), 0, st>>>(g, tiles);
+    const int32_t grid = workers < tiles ? workers : (int32_t)tiles;
+    group_gemm_kernel<<<dim3((unsigned)grid), dim3(kThreads), 0, st>>>(g);
     return hipGetLastError();
 }
 

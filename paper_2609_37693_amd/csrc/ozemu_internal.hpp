@@ -205,10 +205,26 @@ __host__ __device__ __forceinline__ uint32_t trunc_residue(uint64_t mant, int sh
 // The work of each phase is a list of workgroups, problem after problem:
 // prefix[kind * (count + 1) + p] is the first workgroup of problem p and
 // prefix[kind * (count + 1) + count] the total. The GEMM's work items
-// (modulus, tile) follow the problems in `order` (descending K), so the
-// longest tiles are taken first by the persistent workgroups.
+// (modulus, tile) are split into one list per XCD (kind kGTiles + x): each
+// (problem, modulus) gives every XCD a contiguous eighth of its tiles in
+// band order, so the workgroups of one XCD share operand strips in its L2.
+// The lists follow the problems in `order` (descending K), so the longest
+// tiles are taken first.
 constexpr int kMaxGroup = 4096;  // problems per group (two 64-wide ballots)
-enum GKind : int { kGColInit = 0, kGRows, kGCols, kGShifts, kGEncA, kGEncB, kGTiles, kGCrt, kGKinds };
+constexpr int kXcds = 8;
+enum GKind : int {
+    kGColInit = 0, kGRows, kGCols, kGShifts, kGEncA, kGEncB, kGCrt, kGTiles,
+    kGKinds = kGTiles + kXcds
+};
+
+// Tiles [lo, hi) of T that XCD x takes for the q-th problem in GEMM order
+// (the eighths rotate with q so that remainders spread over the XCDs).
+__host__ __device__ __forceinline__ void xcd_share(int64_t T, int x, int q, int64_t& lo,
+                                                   int64_t& hi) {
+    const int r = (x + q) & (kXcds - 1);
+    lo = (int64_t)r * T / kXcds;
+    hi = (int64_t)(r + 1) * T / kXcds;
+}
 
 struct GProblem {
     int64_t m, n, k, m_pad, n_pad, k_pad;
@@ -228,7 +244,7 @@ struct GroupArgs {
     const int32_t* prefix;  // [kGKinds][count + 1]
     const int32_t* order;   // problems in GEMM work order
     char* ws;
-    int32_t* counter;       // persistent GEMM work counter
+    int32_t* counter;       // persistent GEMM work counters, one per XCD
     int32_t count;
 };
 
@@ -303,8 +319,10 @@ hipError_t launch_zero_c(hipStream_t st, int64_t m, int64_t n, double* C, int64_
 hipError_t launch_group_init(hipStream_t st, const GroupArgs& g, int32_t total);
 hipError_t launch_group_scale(hipStream_t st, const GroupArgs& g, int32_t rows, int32_t cols,
                               int32_t shifts);
-hipError_t launch_group_encode(hipStream_t st, const GroupArgs& g, int32_t enc_a, int32_t enc_b);
-hipError_t launch_group_gemm(hipStream_t st, const GroupArgs& g, int32_t tiles, int32_t workers);
+hipError_t launch_group_encode(hipStream_t st, const GroupArgs& g, int32_t enc_a, int32_t enc_b,
+                               bool big);
+hipError_t launch_group_gemm(hipStream_t st, const GroupArgs& g, const int32_t* tiles_per_xcd,
+                             int32_t workers);
 hipError_t launch_group_reconstruct(hipStream_t st, const GroupArgs& g, int32_t blocks, int dmax);
 
 }  // namespace ozemu

@@ -195,9 +195,9 @@ __global__ void bound_shifts_kernel(int64_t count, const int32_t* key, const int
 // ---- Grouped Scale ----
 
 // Column keys of every problem pre-filled with kKeyZero (256 per
-// workgroup); workgroup 0 also zeroes the GEMM work counter.
+// workgroup); workgroup 0 also zeroes the GEMM work counters.
 __global__ __launch_bounds__(kScaleThreads) void group_init_kernel(GroupArgs g, int32_t total) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *g.counter = 0;
+    if (blockIdx.x == 0 && threadIdx.x < kXcds) g.counter[threadIdx.x] = 0;
     if ((int32_t)blockIdx.x >= total) return;
     const int32_t* pre = g.prefix + kGColInit * (g.count + 1);
     const int p = group_find(pre, g.count, blockIdx.x);
