@@ -49,7 +49,10 @@ typedef enum {
 
 /* Low-precision format of the residue GEMMs (Sec. III-A alphabets). */
 typedef enum {
-    OZEMU_INT8 = 0  /* one INT8 GEMM per modulus, moduli <= 256 (Sec. IV-C) */
+    OZEMU_INT8 = 0,  /* one INT8 GEMM per modulus, moduli <= 256 (Sec. IV-C)      */
+    OZEMU_E4M3 = 1,  /* FP8 limb channels, FP32 accumulation (Sec. III-B, IV-A)  */
+    OZEMU_E2M3 = 2,  /* FP6: not built (OZEMU_ERR_UNSUPPORTED)                   */
+    OZEMU_E2M1 = 3   /* FP4 limb channels, FP32 accumulation (Sec. III-B, IV-B)  */
 } ozemu_format;
 
 /* How many bits of each row of A / column of B are kept (Sec. II-A).
@@ -83,6 +86,32 @@ ozemu_status ozemu_plan_create(ozemu_plan* out, int format, int num_moduli, int 
  * coprime, each in [2, 256]; any order; stored sorted descending). */
 ozemu_status ozemu_plan_create_moduli(ozemu_plan* out, int format, int count,
                                       const int32_t* moduli, int scaling);
+
+/* Plan over limb channels of a float alphabet (format OZEMU_E4M3 or
+ * OZEMU_E2M1), for ozemu_dgemm (the other entry points take INT8 plans).
+ * The accumulation slab is k_slab terms (a multiple of 128, at most 2^24):
+ * every stored plane value lies within r = floor(sqrt(2^24 / k_slab)), so
+ * each FP32 accumulator stays exact (eq. "ov-accgen"); a longer k runs in
+ * slabs whose residues add modulo m (Sec. V-B). The pool holds, per
+ * modulus, the one-limb form if the alphabet within r meets every class,
+ * else the two-limb Toom form at points 0, 1, infinity (three GEMMs,
+ * weights 1 - b, b, b^2 - b) at the least base b that does and meets the
+ * reduce-then-combine bound (eq. "ov-comrtc"). From the pool, pairwise-
+ * coprime channels: with gemms > 0 the largest modulus product within
+ * that many GEMMs (the accuracy knob of mode WINDOW); with gemms = 0 the
+ * least GEMM count whose product exceeds k_slab * 2^107 (the window of
+ * eq. "ov-crt" at K = k_slab, as Table "moduli" counts). Ties between
+ * products are decided on a 32-fraction-bit fixed-point log2 computed by
+ * repeated squaring, the first candidate in a fixed order winning. */
+ozemu_status ozemu_plan_create_fp(ozemu_plan* out, int format, int gemms, int64_t k_slab,
+                                  int scaling);
+
+/* Channels of a plan into host arrays of capacity `cap` (any may be NULL):
+ * modulus, rank (GEMMs: 1 one-limb, 3 two-limb Toom) and base (0 for one
+ * limb), by decreasing modulus; an INT8 plan reports its moduli at rank 1.
+ * *count receives the number of channels. */
+ozemu_status ozemu_plan_channels(ozemu_plan plan, int32_t* moduli, int32_t* ranks,
+                                 int32_t* bases, int cap, int* count);
 
 ozemu_status ozemu_plan_destroy(ozemu_plan plan);
 

@@ -233,7 +233,7 @@ def configuration(fmt: str, k_slab: int, q: int | None = None, window_k: int | N
     given, else the largest-product set within q GEMMs."""
     mem = pool(fmt, k_slab)
     if window_k is not None:
-        return select(mem, q if q is not None else 40, target=int(window_k) * 2 ** 107)
+        return select(mem, q if q is not None else 96, target=int(window_k) * 2 ** 107)
     return select(mem, q)
 
 

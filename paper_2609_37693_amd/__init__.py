@@ -25,14 +25,22 @@ def version() -> str:
 
 
 class Plan:
-    """An emulation plan: modulus set, scaling mode, CRT constants (host)."""
+    """An emulation plan: modulus set (INT8) or limb channels of a float
+    alphabet (format "E4M3" or "E2M1", ``gemms`` GEMMs, slabs of ``k_slab``
+    terms; gemms = 0 takes the least count for the window at K = k_slab),
+    scaling mode, CRT constants (host)."""
 
-    def __init__(self, num_moduli: int = 16, scaling: str = "W", moduli=None):
+    def __init__(self, num_moduli: int = 16, scaling: str = "W", moduli=None,
+                 format: str = "INT8", gemms: int = 0, k_slab: int = 16384):
         lib = _lib.load()
         self._h = C.c_void_p()
         self.scaling = scaling
+        self.format = format
         mode = SCALING[scaling]
-        if moduli is not None:
+        if format != "INT8":
+            _lib.check(lib.ozemu_plan_create_fp(C.byref(self._h), _lib.FORMATS[format],
+                                                int(gemms), int(k_slab), mode))
+        elif moduli is not None:
             arr = (C.c_int32 * len(moduli))(*[int(m) for m in moduli])
             _lib.check(lib.ozemu_plan_create_moduli(C.byref(self._h), _lib.OZEMU_INT8,
                                                     len(moduli), arr, mode))
@@ -57,6 +65,19 @@ class Plan:
         out = (C.c_int32 * cnt.value)()
         _lib.check(self._lib.ozemu_plan_moduli(self._h, out, cnt.value, C.byref(cnt)))
         return list(out)
+
+    def channels(self):
+        """[(modulus, rank, base)] by decreasing modulus (rank: GEMMs per
+        channel; base 0 for one limb)."""
+        cnt = C.c_int()
+        _lib.check(self._lib.ozemu_plan_channels(self._h, None, None, None, 0, C.byref(cnt)))
+        n = cnt.value
+        ms, rs, bs = (C.c_int32 * n)(), (C.c_int32 * n)(), (C.c_int32 * n)()
+        _lib.check(self._lib.ozemu_plan_channels(self._h, ms, rs, bs, n, C.byref(cnt)))
+        return [(ms[i], rs[i], bs[i]) for i in range(n)]
+
+    def gemms(self) -> int:
+        return sum(r for _, r, _ in self.channels())
 
     def kept_bits(self, k: int):
         a, b = C.c_int(), C.c_int()

@@ -19,6 +19,7 @@ OZEMU_ERR_WORKSPACE = -4
 OZEMU_ERR_HIP = -5
 
 OZEMU_INT8 = 0
+FORMATS = {"INT8": 0, "E4M3": 1, "E2M3": 2, "E2M1": 3}
 SCALING = {"F53": 0, "W": 1, "G": 2}
 SHIFT_NONFINITE = -(2 ** 31)
 
@@ -31,6 +32,9 @@ SIGNATURES = {
     "ozemu_plan_create": (_st, [C.POINTER(_vp), C.c_int, C.c_int, C.c_int]),
     "ozemu_plan_create_moduli": (_st, [C.POINTER(_vp), C.c_int, C.c_int,
                                        C.POINTER(C.c_int32), C.c_int]),
+    "ozemu_plan_create_fp": (_st, [C.POINTER(_vp), C.c_int, C.c_int, _i64, C.c_int]),
+    "ozemu_plan_channels": (_st, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                  C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_int)]),
     "ozemu_plan_destroy": (_st, [_vp]),
     "ozemu_plan_moduli": (_st, [_vp, C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_int)]),
     "ozemu_plan_kept_bits": (_st, [_vp, _i64, C.POINTER(C.c_int), C.POINTER(C.c_int)]),

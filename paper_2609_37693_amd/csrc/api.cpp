@@ -57,13 +57,28 @@ Dims dims_of(int64_t m, int64_t n, int64_t k) {
     return {round_up(m, ozemu::kTileM), round_up(n, ozemu::kTileN), round_up(k, ozemu::kTileK)};
 }
 
+// Float-channel plans: K padded to whole 64-byte plane blocks (128 values
+// for FP4, two per byte).
+Dims dims_of(const ozemu::Plan& p, int64_t m, int64_t n, int64_t k) {
+    if (p.format == OZEMU_E2M1)
+        return {round_up(m, ozemu::kTileM), round_up(n, ozemu::kTileN), round_up(k, 128)};
+    return dims_of(m, n, k);
+}
+
+bool is_fp(const ozemu::Plan& p) { return p.format != OZEMU_INT8; }
+
+// bytes of a float plane row of k_pad values
+int64_t fp_row_bytes(const ozemu::Plan& p, int64_t k_pad) {
+    return p.format == OZEMU_E2M1 ? k_pad / 2 : k_pad;
+}
+
 struct Layout {
     size_t key_a, key_b, shift_a, shift_b, planes_a, planes_b, residues, bar_a, bar_b, gmax_a,
-        gmax_b, total;
+        gmax_b, tables, total;
 };
 
 Layout layout_of(const ozemu::Plan& p, int64_t m, int64_t n, int64_t k) {
-    Dims d = dims_of(m, n, k);
+    Dims d = dims_of(p, m, n, k);
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -72,6 +87,17 @@ Layout layout_of(const ozemu::Plan& p, int64_t m, int64_t n, int64_t k) {
         return at;
     };
     const size_t N = (size_t)p.n;
+    if (is_fp(p)) {
+        const size_t planes = (size_t)p.fp.planes, kb = (size_t)fp_row_bytes(p, d.k_pad);
+        L.shift_a = take(sizeof(int32_t) * (size_t)d.m_pad);
+        L.shift_b = take(sizeof(int32_t) * (size_t)d.n_pad);
+        L.tables = take(p.tables.size());
+        L.planes_a = take(planes * (size_t)d.m_pad * kb);
+        L.planes_b = take(planes * (size_t)d.n_pad * kb);
+        L.residues = take(sizeof(uint16_t) * N * (size_t)d.m_pad * (size_t)d.n_pad);
+        L.total = off;
+        return L;
+    }
     L.key_a = take(sizeof(int32_t) * (size_t)d.m_pad);
     L.key_b = take(sizeof(int32_t) * (size_t)d.n_pad);
     L.shift_a = take(sizeof(int32_t) * (size_t)d.m_pad);
@@ -112,6 +138,15 @@ ozemu_status check_shape(const ozemu::Plan& p, int64_t m, int64_t n, int64_t k) 
                         " exceeds the reconstruction cap of this modulus set at 53 bits");
     if (p.scaling == OZEMU_SCALE_WINDOW && k > 0 && ozemu::window_bits(p, k) < 2)
         return fail(OZEMU_ERR_K_TOO_LARGE, "modulus product too small for this k");
+    if (is_fp(p) && k > 0) {
+        int ba = 53, bb = 53;
+        if (p.scaling == OZEMU_SCALE_WINDOW) {
+            const int w = ozemu::window_bits(p, k);
+            ba = (w + 1) / 2, bb = w / 2;
+        }
+        if (ba > 63 || bb > 63)
+            return fail(OZEMU_ERR_UNSUPPORTED, "float-channel plans keep at most 63 bits per entry");
+    }
     if (p.scaling == OZEMU_SCALE_BOUND && k > 524287)
         return fail(OZEMU_ERR_K_TOO_LARGE, "bound product would overflow INT32");
     return ok();
@@ -216,6 +251,7 @@ int backward_bits(const ozemu::Plan& p, int64_t inner, int cached) {
 }
 
 ozemu_status check_cache_plan(const ozemu::Plan& p, int64_t m, int64_t n, int64_t k) {
+    if (is_fp(p)) return fail(OZEMU_ERR_UNSUPPORTED, "cached forward and backward take INT8 plans");
     if (p.scaling == OZEMU_SCALE_BOUND)
         return fail(OZEMU_ERR_UNSUPPORTED, "cached forward and backward support F53 and WINDOW");
     if (m < 0 || n < 0 || k < 0) return fail(OZEMU_ERR_INVALID_ARG, "negative dimension");
@@ -278,7 +314,8 @@ ozemu_status ozemu_plan_create_moduli(ozemu_plan* out, int format, int count,
                                       const int32_t* moduli, int scaling) {
     if (!out) return fail(OZEMU_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
-    if (format != OZEMU_INT8) return fail(OZEMU_ERR_UNSUPPORTED, "only OZEMU_INT8 is built");
+    if (format != OZEMU_INT8)
+        return fail(OZEMU_ERR_UNSUPPORTED, "modulus plans are INT8; float formats: ozemu_plan_create_fp");
     if (count < 2 || count > ozemu::kMaxModuli || !moduli)
         return fail(OZEMU_ERR_INVALID_ARG, "number of moduli must be in [2, 32]");
     std::vector<int> ms(moduli, moduli + count);
@@ -296,7 +333,8 @@ ozemu_status ozemu_plan_create_moduli(ozemu_plan* out, int format, int count,
 ozemu_status ozemu_plan_create(ozemu_plan* out, int format, int num_moduli, int scaling) {
     if (!out) return fail(OZEMU_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
-    if (format != OZEMU_INT8) return fail(OZEMU_ERR_UNSUPPORTED, "only OZEMU_INT8 is built");
+    if (format != OZEMU_INT8)
+        return fail(OZEMU_ERR_UNSUPPORTED, "modulus plans are INT8; float formats: ozemu_plan_create_fp");
     if (num_moduli < 2 || num_moduli > ozemu::kMaxModuli)
         return fail(OZEMU_ERR_INVALID_ARG, "number of moduli must be in [2, 32]");
     std::vector<int> ms = ozemu::best_coprime_set(num_moduli, 256);
@@ -305,7 +343,43 @@ ozemu_status ozemu_plan_create(ozemu_plan* out, int format, int num_moduli, int 
     return ozemu_plan_create_moduli(out, format, num_moduli, m32.data(), scaling);
 }
 
+ozemu_status ozemu_plan_create_fp(ozemu_plan* out, int format, int gemms, int64_t k_slab,
+                                  int scaling) {
+    if (!out) return fail(OZEMU_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (format != OZEMU_E4M3 && format != OZEMU_E2M1)
+        return fail(OZEMU_ERR_UNSUPPORTED, "float plans are built for OZEMU_E4M3 and OZEMU_E2M1");
+    ozemu_plan p = new (std::nothrow) ozemu_plan_s;
+    if (!p) return fail(OZEMU_ERR_INVALID_ARG, "out of host memory");
+    std::string err = ozemu::build_plan_fp(p->p, format, gemms, k_slab, scaling);
+    if (!err.empty()) {
+        delete p;
+        return fail(OZEMU_ERR_INVALID_ARG, err);
+    }
+    *out = p;
+    return ok();
+}
+
+ozemu_status ozemu_plan_channels(ozemu_plan plan, int32_t* moduli, int32_t* ranks,
+                                 int32_t* bases, int cap, int* count) {
+    if (ozemu_status s = check_plan(plan)) return s;
+    if (!count) return fail(OZEMU_ERR_INVALID_ARG, "count is NULL");
+    const ozemu::Plan& p = plan->p;
+    *count = p.n;
+    if (moduli || ranks || bases) {
+        if (cap < p.n) return fail(OZEMU_ERR_INVALID_ARG, "capacity too small");
+        for (int i = 0; i < p.n; ++i) {
+            const bool fp = is_fp(p);
+            if (moduli) moduli[i] = fp ? p.chans[i].m : p.moduli[i];
+            if (ranks) ranks[i] = fp ? p.chans[i].rank : 1;
+            if (bases) bases[i] = fp ? p.chans[i].base : 0;
+        }
+    }
+    return ok();
+}
+
 ozemu_status ozemu_plan_destroy(ozemu_plan plan) {
+    if (plan && plan->p.pinned_tables) (void)hipHostFree(plan->p.pinned_tables);
     delete plan;
     return ok();
 }
@@ -357,7 +431,7 @@ ozemu_status ozemu_plane_dims(ozemu_plan plan, int64_t m, int64_t n, int64_t k, 
                               int64_t* n_pad, int64_t* k_pad) {
     if (ozemu_status s = check_plan(plan)) return s;
     if (m < 0 || n < 0 || k < 0) return fail(OZEMU_ERR_INVALID_ARG, "negative dimension");
-    Dims d = dims_of(m, n, k);
+    Dims d = dims_of(plan->p, m, n, k);
     if (m_pad) *m_pad = d.m_pad;
     if (n_pad) *n_pad = d.n_pad;
     if (k_pad) *k_pad = d.k_pad;
@@ -396,6 +470,7 @@ ozemu_status ozemu_reduce(ozemu_plan plan, void* stream, int64_t m, int64_t n, i
                           int8_t* planes_b) {
     if (ozemu_status s = check_plan(plan)) return s;
     const ozemu::Plan& p = plan->p;
+    if (is_fp(p)) return fail(OZEMU_ERR_UNSUPPORTED, "phase calls take INT8 plans");
     if (ozemu_status s = check_shape(p, m, n, k)) return s;
     if (ozemu_status s = check_operands(m, n, k, A, lda, B, ldb)) return s;
     Dims d = dims_of(m, n, k);
@@ -424,6 +499,7 @@ ozemu_status ozemu_residue_gemm(ozemu_plan plan, void* stream, int64_t m, int64_
                                 uint8_t* residues) {
     if (ozemu_status s = check_plan(plan)) return s;
     const ozemu::Plan& p = plan->p;
+    if (is_fp(p)) return fail(OZEMU_ERR_UNSUPPORTED, "phase calls take INT8 plans");
     if (ozemu_status s = check_shape(p, m, n, k)) return s;
     Dims d = dims_of(m, n, k);
     if (d.m_pad == 0 || d.n_pad == 0) return ok();
@@ -446,6 +522,7 @@ ozemu_status ozemu_reconstruct(ozemu_plan plan, void* stream, int64_t m, int64_t
                                const int32_t* shift_b, double* C, int64_t ldc) {
     if (ozemu_status s = check_plan(plan)) return s;
     const ozemu::Plan& p = plan->p;
+    if (is_fp(p)) return fail(OZEMU_ERR_UNSUPPORTED, "phase calls take INT8 plans");
     if (ozemu_status s = check_shape(p, m, n, k)) return s;
     if (m == 0 || n == 0) return ok();
     if (!C || ldc < n) return fail(OZEMU_ERR_INVALID_ARG, "C is NULL or ldc < n");
@@ -456,6 +533,81 @@ ozemu_status ozemu_reconstruct(ozemu_plan plan, void* stream, int64_t m, int64_t
                                                residues, shift_a, shift_b, C, ldc),
                      "reconstruct");
 }
+
+namespace {
+
+// C = A B through the float channels of plan p (arguments validated).
+ozemu_status dgemm_fp(const ozemu::Plan& p, hipStream_t st, int64_t m, int64_t n, int64_t k,
+                      const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
+                      int64_t ldc, char* ws, const Layout& L) {
+    using namespace ozemu;
+    Dims d = dims_of(p, m, n, k);
+    int32_t* sa = reinterpret_cast<int32_t*>(ws + L.shift_a);
+    int32_t* sb = reinterpret_cast<int32_t*>(ws + L.shift_b);
+    int8_t* pa = reinterpret_cast<int8_t*>(ws + L.planes_a);
+    int8_t* pb = reinterpret_cast<int8_t*>(ws + L.planes_b);
+    uint16_t* z = reinterpret_cast<uint16_t*>(ws + L.residues);
+    uint8_t* tables = reinterpret_cast<uint8_t*>(ws + L.tables);
+    if (ozemu_status s = run_scale(p, st, m, n, k, A, lda, B, ldb, sa, sb, ws)) return s;
+    ozemu::Plan& mp = const_cast<ozemu::Plan&>(p);
+    if (!mp.pinned_tables) {
+        uint8_t* h = nullptr;
+        if (ozemu_status s = hip_check(hipHostMalloc((void**)&h, p.tables.size(),
+                                                     hipHostMallocDefault),
+                                       "pinned channel tables"))
+            return s;
+        std::memcpy(h, p.tables.data(), p.tables.size());
+        mp.pinned_tables = h;
+    }
+    if (ozemu_status s = hip_check(hipMemcpyAsync(tables, p.pinned_tables, p.tables.size(),
+                                                  hipMemcpyHostToDevice, st),
+                                   "channel tables"))
+        return s;
+    if (ozemu_status s = hip_check(
+            launch_encode_fp(st, p.fp, tables, (int)p.tables.size(), m, n, k, A, lda, B, ldb, sa,
+                             sb, d.m_pad, d.n_pad, d.k_pad, pa, pb),
+            "encode_fp"))
+        return s;
+    const int64_t kb_pad = fp_row_bytes(p, d.k_pad);
+    const int64_t slab_b = fp_row_bytes(p, p.k_slab);
+    const int64_t tiles = (d.m_pad / kTileM) * (d.n_pad / kTileN);
+    for (int64_t kb0 = 0; kb0 < kb_pad; kb0 += slab_b) {
+        for (int r = 0; r < 3; ++r) {
+            FpGemmArgs g{};
+            g.first = (kb0 == 0 && r == 0) ? 1 : 0;
+            g.scale = (float)(1 << (2 * p.fp.es));
+            g.m_pad = d.m_pad;
+            g.n_pad = d.n_pad;
+            g.kb_pad = kb_pad;
+            g.kb_begin = kb0;
+            g.kb_len = std::min(slab_b, kb_pad - kb0);
+            g.pa = pa;
+            g.pb = pb;
+            g.z = z;
+            int cnt = 0;
+            int64_t start = 0;
+            for (int c = 0; c < p.fp.n; ++c) {
+                if (p.fp.rank[c] <= r) continue;
+                g.start[cnt] = start;
+                g.plane[cnt] = p.fp.plane0[c] + r;
+                g.chan[cnt] = c;
+                g.m[cnt] = p.fp.m[c];
+                g.mu[cnt] = p.fp.mu[c];
+                g.lbar[cnt] = p.fp.lbar[c][r];
+                start += tiles;
+                ++cnt;
+            }
+            g.start[cnt] = start;
+            g.count = cnt;
+            if (cnt == 0) continue;
+            if (ozemu_status s = hip_check(launch_fp_gemm(st, g, p.fp.fmt), "fp_gemm")) return s;
+        }
+    }
+    return hip_check(launch_reconstruct16(st, p.crt, m, n, d.m_pad, d.n_pad, z, sa, sb, C, ldc),
+                     "reconstruct");
+}
+
+}  // namespace
 
 ozemu_status ozemu_dgemm(ozemu_plan plan, void* stream, int64_t m, int64_t n, int64_t k,
                          const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
@@ -474,6 +626,7 @@ ozemu_status ozemu_dgemm(ozemu_plan plan, void* stream, int64_t m, int64_t n, in
     if (reinterpret_cast<uintptr_t>(workspace) & 255)
         return fail(OZEMU_ERR_WORKSPACE, "workspace is not 256-byte aligned");
     char* ws = static_cast<char*>(workspace);
+    if (is_fp(p)) return dgemm_fp(p, st, m, n, k, A, lda, B, ldb, C, ldc, ws, L);
     int32_t* sa = reinterpret_cast<int32_t*>(ws + L.shift_a);
     int32_t* sb = reinterpret_cast<int32_t*>(ws + L.shift_b);
     int8_t* pa = reinterpret_cast<int8_t*>(ws + L.planes_a);
@@ -525,6 +678,8 @@ ozemu_status ozemu_group_create(ozemu_group* out, int count, const ozemu_plan* p
     for (int p = 0; p < count; ++p) {
         if (!plans[p]) return fail(OZEMU_ERR_INVALID_ARG, "plan of problem " + std::to_string(p) + " is NULL");
         const Plan* pl = &plans[p]->p;
+        if (pl->format != OZEMU_INT8)
+            return fail(OZEMU_ERR_UNSUPPORTED, "grouped products take INT8 plans");
         if (pl->scaling == OZEMU_SCALE_BOUND)
             return fail(OZEMU_ERR_UNSUPPORTED, "grouped products support F53 and WINDOW");
         int at = -1;

@@ -100,10 +100,11 @@ __device__ __forceinline__ double finish_one(const CrtConsts& cc, int64_t* acc, 
 }
 
 // Thread g of the output: row g / ceil(n / 4), four consecutive columns.
-template <int D>
+// Residues are uint8 (INT8 moduli) or uint16 (float-channel moduli).
+template <int D, typename R = uint8_t>
 __device__ __forceinline__ void reconstruct_body(const CrtConsts& cc, int64_t m, int64_t n,
                                                  int64_t m_pad, int64_t n_pad,
-                                                 const uint8_t* __restrict__ Z,
+                                                 const R* __restrict__ Z,
                                                  const int32_t* __restrict__ sa,
                                                  const int32_t* __restrict__ sb,
                                                  double* __restrict__ C, int64_t ldc, int64_t g) {
@@ -120,14 +121,25 @@ __device__ __forceinline__ void reconstruct_body(const CrtConsts& cc, int64_t m,
 #pragma unroll
         for (int d = 0; d < D; ++d) acc[c][d] = 0;
     }
-    const uint8_t* zp = Z + i * n_pad + j0;
+    const R* zp = Z + i * n_pad + j0;
     for (int l = 0; l < cc.n; ++l) {
-        const uint32_t word = *reinterpret_cast<const uint32_t*>(zp + (int64_t)l * plane);
+        uint32_t zv[kPerThread];
+        if constexpr (sizeof(R) == 1) {
+            const uint32_t word = *reinterpret_cast<const uint32_t*>(zp + (int64_t)l * plane);
+#pragma unroll
+            for (int c = 0; c < kPerThread; ++c) zv[c] = (word >> (8 * c)) & 0xFFu;
+        } else {
+            const uint2 w2 = *reinterpret_cast<const uint2*>(zp + (int64_t)l * plane);
+            zv[0] = w2.x & 0xFFFFu;
+            zv[1] = w2.x >> 16;
+            zv[2] = w2.y & 0xFFFFu;
+            zv[3] = w2.y >> 16;
+        }
         const uint32_t ml = cc.m[l], mu = cc.mu[l], inv = cc.inv[l];
         const double rcp = cc.rcp[l];
 #pragma unroll
         for (int c = 0; c < kPerThread; ++c) {
-            const uint64_t u = barrett32(((word >> (8 * c)) & 0xFFu) * inv, ml, mu);
+            const uint64_t u = barrett32(zv[c] * inv, ml, mu);
             f[c] += (double)u * rcp;
 #pragma unroll
             for (int d = 0; d < D; ++d) acc[c][d] += (int64_t)(u * cc.Ml[l][d]);
@@ -156,14 +168,14 @@ __device__ __forceinline__ void reconstruct_body(const CrtConsts& cc, int64_t m,
     }
 }
 
-template <int D>
+template <int D, typename R>
 __global__ __launch_bounds__(kThreads) void reconstruct_kernel(CrtConsts cc, int64_t m, int64_t n,
                                                                int64_t m_pad, int64_t n_pad,
-                                                               const uint8_t* __restrict__ Z,
+                                                               const R* __restrict__ Z,
                                                                const int32_t* __restrict__ sa,
                                                                const int32_t* __restrict__ sb,
                                                                double* __restrict__ C, int64_t ldc) {
-    reconstruct_body<D>(cc, m, n, m_pad, n_pad, Z, sa, sb, C, ldc,
+    reconstruct_body<D, R>(cc, m, n, m_pad, n_pad, Z, sa, sb, C, ldc,
                         (int64_t)blockIdx.x * kThreads + threadIdx.x);
 }
 
@@ -200,15 +212,34 @@ hipError_t launch_group_d(hipStream_t st, const GroupArgs& g, int32_t blocks) {
     return hipGetLastError();
 }
 
-template <int D>
+template <int D, typename R>
 hipError_t launch_d(hipStream_t st, const CrtConsts& cc, int64_t m, int64_t n, int64_t m_pad,
-                    int64_t n_pad, const uint8_t* Z, const int32_t* sa, const int32_t* sb,
+                    int64_t n_pad, const R* Z, const int32_t* sa, const int32_t* sb,
                     double* C, int64_t ldc) {
     const int64_t threads = m * ((n + kPerThread - 1) / kPerThread);
     const int64_t blocks = (threads + kThreads - 1) / kThreads;
-    reconstruct_kernel<D><<<dim3((unsigned)blocks), dim3(kThreads), 0, st>>>(cc, m, n, m_pad, n_pad,
-                                                                             Z, sa, sb, C, ldc);
+    reconstruct_kernel<D, R><<<dim3((unsigned)blocks), dim3(kThreads), 0, st>>>(
+        cc, m, n, m_pad, n_pad, Z, sa, sb, C, ldc);
     return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_any(hipStream_t st, const CrtConsts& cc, int64_t m, int64_t n, int64_t m_pad,
+                      int64_t n_pad, const R* Z, const int32_t* sa, const int32_t* sb, double* C,
+                      int64_t ldc) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    switch (cc.d) {
+        case 2: return launch_d<2, R>(st, cc, m, n, m_pad, n_pad, Z, sa, sb, C, ldc);
+        case 3: return launch_d<3, R>(st, cc, m, n, m_pad, n_pad, Z, sa, sb, C, ldc);
+        case 4: return launch_d<4, R>(st, cc, m, n, m_pad, n_pad, Z, sa, sb, C, ldc);
+        case 5: return launch_d<5, R>(st, cc, m, n, m_pad, n_pad, Z, sa, sb, C, ldc);
+        case 6: return launch_d<6, R>(st, cc, m, n, m_pad, n_pad, Z, sa, sb, C, ldc);
+        case 7: return launch_d<7, R>(st, cc, m, n, m_pad, n_pad, Z, sa, sb, C, ldc);
+        case 8: return launch_d<8, R>(st, cc, m, n, m_pad, n_pad, Z, sa, sb, C, ldc);
+        case 9: return launch_d<9, R>(st, cc, m, n, m_pad, n_pad, Z, sa, sb, C, ldc);
+        case 10: return launch_d<10, R>(st, cc, m, n, m_pad, n_pad, Z, sa, sb, C, ldc);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
@@ -217,19 +248,14 @@ hipError_t launch_reconstruct(hipStream_t st, const CrtConsts& cc, int64_t m, in
                               int64_t m_pad, int64_t n_pad, const uint8_t* residues,
                               const int32_t* shift_a, const int32_t* shift_b, double* C,
                               int64_t ldc) {
-    if (m <= 0 || n <= 0) return hipSuccess;
-    switch (cc.d) {
-        case 2: return launch_d<2>(st, cc, m, n, m_pad, n_pad, residues, shift_a, shift_b, C, ldc);
-        case 3: return launch_d<3>(st, cc, m, n, m_pad, n_pad, residues, shift_a, shift_b, C, ldc);
-        case 4: return launch_d<4>(st, cc, m, n, m_pad, n_pad, residues, shift_a, shift_b, C, ldc);
-        case 5: return launch_d<5>(st, cc, m, n, m_pad, n_pad, residues, shift_a, shift_b, C, ldc);
-        case 6: return launch_d<6>(st, cc, m, n, m_pad, n_pad, residues, shift_a, shift_b, C, ldc);
-        case 7: return launch_d<7>(st, cc, m, n, m_pad, n_pad, residues, shift_a, shift_b, C, ldc);
-        case 8: return launch_d<8>(st, cc, m, n, m_pad, n_pad, residues, shift_a, shift_b, C, ldc);
-        case 9: return launch_d<9>(st, cc, m, n, m_pad, n_pad, residues, shift_a, shift_b, C, ldc);
-        case 10: return launch_d<10>(st, cc, m, n, m_pad, n_pad, residues, shift_a, shift_b, C, ldc);
-        default: return hipErrorInvalidValue;
-    }
+    return launch_any<uint8_t>(st, cc, m, n, m_pad, n_pad, residues, shift_a, shift_b, C, ldc);
+}
+
+hipError_t launch_reconstruct16(hipStream_t st, const CrtConsts& cc, int64_t m, int64_t n,
+                                int64_t m_pad, int64_t n_pad, const uint16_t* residues,
+                                const int32_t* shift_a, const int32_t* shift_b, double* C,
+                                int64_t ldc) {
+    return launch_any<uint16_t>(st, cc, m, n, m_pad, n_pad, residues, shift_a, shift_b, C, ldc);
 }
 
 hipError_t launch_group_reconstruct(hipStream_t st, const GroupArgs& g, int32_t blocks, int dmax) {

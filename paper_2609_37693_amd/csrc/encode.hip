@@ -241,6 +241,143 @@ __global__ __launch_bounds__(kEncThreads) void encode_b_kernel(ModConsts mc, int
                                blockIdx.y, tile, p2);
 }
 
+// ---- Reduce for float-alphabet channels ----
+// Each entry's class modulo every channel (12-bit digit sums and a Barrett
+// step, m < 2^16), then the format codes of the class's plane values from
+// the channel's table (in LDS) into every plane: one byte per entry for
+// FP8, one nibble for FP4 (entry h in nibble h % 2 of byte h / 2, low
+// first). Planes use the block order of plane_offset over the planes' byte
+// extent kb_pad (k_pad for FP8, k_pad / 2 for FP4).
+
+__device__ __forceinline__ uint32_t fp_class(const Digits12& g, bool neg, const FpConsts& fc,
+                                             int c) {
+    const uint16_t* w = fc.w12[c];
+    uint32_t t = g.d[0];
+    t = __umul24(g.d[1], w[1]) + t;
+    t = __umul24(g.d[2], w[2]) + t;
+    t = __umul24(g.d[3], w[3]) + t;
+    t = __umul24(g.d[4], w[4]) + t;
+    t = __umul24(g.d[5], w[5]) + t;
+    const uint32_t m = fc.m[c];
+    uint32_t r = barrett32(t, m, fc.mu[c]);
+    return (neg && r) ? m - r : r;
+}
+
+__device__ __forceinline__ void load_tables(const uint8_t* tables, int bytes, uint8_t* lds) {
+    for (int i = threadIdx.x * 4; i < bytes; i += kEncThreads * 4) {
+        if (i + 4 <= bytes) {
+            *reinterpret_cast<uint32_t*>(lds + i) = *reinterpret_cast<const uint32_t*>(tables + i);
+        } else {
+            for (int q = i; q < bytes; ++q) lds[q] = tables[q];
+        }
+    }
+    __syncthreads();
+}
+
+// Codes of 16 consecutive entries into plane p at (row, h): 16 bytes (FP8)
+// or 8 bytes (FP4).
+template <bool kFp4>
+__device__ __forceinline__ void store_codes(int8_t* plane, int64_t row, int64_t h, int64_t kb_pad,
+                                            const uint8_t* code) {
+    if constexpr (!kFp4) {
+        uint4 w;
+        w.x = code[0] | (code[1] << 8) | (code[2] << 16) | ((uint32_t)code[3] << 24);
+        w.y = code[4] | (code[5] << 8) | (code[6] << 16) | ((uint32_t)code[7] << 24);
+        w.z = code[8] | (code[9] << 8) | (code[10] << 16) | ((uint32_t)code[11] << 24);
+        w.w = code[12] | (code[13] << 8) | (code[14] << 16) | ((uint32_t)code[15] << 24);
+        *reinterpret_cast<uint4*>(plane + plane_offset(row, h, kb_pad)) = w;
+    } else {
+        uint32_t lo = 0, hi = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) lo |= (uint32_t)(code[q] & 15u) << (4 * q);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) hi |= (uint32_t)(code[8 + q] & 15u) << (4 * q);
+        *reinterpret_cast<uint2*>(plane + plane_offset(row, h / 2, kb_pad)) = make_uint2(lo, hi);
+    }
+}
+
+// A side: thread handles a 16-entry chunk of a row (chunks cross rows as in
+// encode_a). Dynamic LDS: the table blob.
+template <bool kFp4>
+__global__ __launch_bounds__(kEncThreads) void encode_fp_a_kernel(
+    FpConsts fc, const uint8_t* tables, int table_bytes, int64_t m, int64_t k, const double* A,
+    int64_t lda, const int32_t* shift_a, int64_t m_pad, int64_t k_pad, int8_t* planes) {
+    extern __shared__ uint8_t tab[];
+    load_tables(tables, table_bytes, tab);
+    const int64_t kb_pad = kFp4 ? k_pad / 2 : k_pad;
+    const int64_t plane_stride = m_pad * kb_pad;
+    const int64_t c = (int64_t)blockIdx.x * kChunksPerBlock + threadIdx.x;
+    const int64_t cpr = k_pad / kEncVec;
+    const int64_t i = c / cpr;
+    const int64_t h = (c % cpr) * kEncVec;
+    if (i >= m_pad) return;
+    uint8_t code[kEncVec];
+    if (i >= m || h >= k) {  // padding: code 0 is +0 in both formats
+        for (int q = 0; q < kEncVec; ++q) code[q] = 0;
+        for (int p = 0; p < fc.planes; ++p) store_codes<kFp4>(planes + p * plane_stride, i, h, kb_pad, code);
+        return;
+    }
+    Entry ent[kEncVec];
+    const int32_t s = shift_a[i];
+    const double* row = A + i * lda;
+#pragma unroll
+    for (int q = 0; q < kEncVec; ++q) {
+        const bool in = h + q < k;
+        ent[q] = make_entry<false>(in ? row[h + q] : 0.0, in ? s : 0);
+    }
+    for (int ch = 0; ch < fc.n; ++ch) {
+        uint32_t cls[kEncVec];
+#pragma unroll
+        for (int q = 0; q < kEncVec; ++q) cls[q] = fp_class(ent[q].g, ent[q].neg, fc, ch);
+        const int rank = fc.rank[ch];
+        const uint8_t* t = tab + fc.toff[ch];
+        for (int r = 0; r < rank; ++r) {
+#pragma unroll
+            for (int q = 0; q < kEncVec; ++q) code[q] = t[cls[q] * rank + r];
+            store_codes<kFp4>(planes + (fc.plane0[ch] + r) * plane_stride, i, h, kb_pad, code);
+        }
+    }
+}
+
+// B side: workgroup (bx, by) covers columns 64 bx .. + 63 and K rows
+// 64 by .. + 63; thread t takes column t % 64 over 16 consecutive K.
+template <bool kFp4>
+__global__ __launch_bounds__(kEncThreads) void encode_fp_b_kernel(
+    FpConsts fc, const uint8_t* tables, int table_bytes, int64_t k, int64_t n, const double* B,
+    int64_t ldb, const int32_t* shift_b, int64_t n_pad, int64_t k_pad, int8_t* planes) {
+    extern __shared__ uint8_t tab[];
+    load_tables(tables, table_bytes, tab);
+    const int64_t kb_pad = kFp4 ? k_pad / 2 : k_pad;
+    const int64_t plane_stride = n_pad * kb_pad;
+    const int64_t j = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+    const int64_t h = (int64_t)blockIdx.y * 64 + (threadIdx.x >> 6) * kEncVec;
+    uint8_t code[kEncVec];
+    if (j >= n || h >= k) {
+        for (int q = 0; q < kEncVec; ++q) code[q] = 0;
+        for (int p = 0; p < fc.planes; ++p) store_codes<kFp4>(planes + p * plane_stride, j, h, kb_pad, code);
+        return;
+    }
+    Entry ent[kEncVec];
+    const int32_t s = shift_b[j];
+#pragma unroll
+    for (int q = 0; q < kEncVec; ++q) {
+        const bool in = h + q < k;
+        ent[q] = make_entry<false>(in ? B[(h + q) * ldb + j] : 0.0, in ? s : 0);
+    }
+    for (int ch = 0; ch < fc.n; ++ch) {
+        uint32_t cls[kEncVec];
+#pragma unroll
+        for (int q = 0; q < kEncVec; ++q) cls[q] = fp_class(ent[q].g, ent[q].neg, fc, ch);
+        const int rank = fc.rank[ch];
+        const uint8_t* t = tab + fc.toff[ch];
+        for (int r = 0; r < rank; ++r) {
+#pragma unroll
+            for (int q = 0; q < kEncVec; ++q) code[q] = t[cls[q] * rank + r];
+            store_codes<kFp4>(planes + (fc.plane0[ch] + r) * plane_stride, j, h, kb_pad, code);
+        }
+    }
+}
+
 // ---- Grouped Reduce ----
 // kBig is chosen for the whole group (the form for kept bits above 63 is
 // exact for any shift, only slower).
@@ -287,6 +424,34 @@ hipError_t launch_group_encode(hipStream_t st, const GroupArgs& g, int32_t enc_a
             group_encode_b_kernel<true><<<dim3((unsigned)enc_b), dim3(kEncThreads), 0, st>>>(g);
         else
             group_encode_b_kernel<false><<<dim3((unsigned)enc_b), dim3(kEncThreads), 0, st>>>(g);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_encode_fp(hipStream_t st, const FpConsts& fc, const uint8_t* tables,
+                            int table_bytes, int64_t m, int64_t n, int64_t k, const double* A,
+                            int64_t lda, const double* B, int64_t ldb, const int32_t* shift_a,
+                            const int32_t* shift_b, int64_t m_pad, int64_t n_pad, int64_t k_pad,
+                            int8_t* planes_a, int8_t* planes_b) {
+    const bool fp4 = fc.fmt == 4;
+    const size_t lds = (size_t)table_bytes;
+    if (m_pad > 0 && k_pad > 0) {
+        dim3 grid((unsigned)((m_pad * (k_pad / kEncVec) + kChunksPerBlock - 1) / kChunksPerBlock));
+        if (fp4)
+            encode_fp_a_kernel<true><<<grid, dim3(kEncThreads), lds, st>>>(
+                fc, tables, table_bytes, m, k, A, lda, shift_a, m_pad, k_pad, planes_a);
+        else
+            encode_fp_a_kernel<false><<<grid, dim3(kEncThreads), lds, st>>>(
+                fc, tables, table_bytes, m, k, A, lda, shift_a, m_pad, k_pad, planes_a);
+    }
+    if (n_pad > 0 && k_pad > 0) {
+        dim3 grid((unsigned)(n_pad / 64), (unsigned)(k_pad / 64));
+        if (fp4)
+            encode_fp_b_kernel<true><<<grid, dim3(kEncThreads), lds, st>>>(
+                fc, tables, table_bytes, k, n, B, ldb, shift_b, n_pad, k_pad, planes_b);
+        else
+            encode_fp_b_kernel<false><<<grid, dim3(kEncThreads), lds, st>>>(
+                fc, tables, table_bytes, k, n, B, ldb, shift_b, n_pad, k_pad, planes_b);
     }
     return hipGetLastError();
 }

@@ -25,6 +25,8 @@ namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int kThreads = 256;
 constexpr int kBM = kTileM;  // rows i per tile
@@ -37,8 +39,11 @@ constexpr int kGroup = 8;  // tile rows per band of the tile order
 // of 66 dwords: the 32 rows a store instruction touches land on even banks
 // and the two lane halves on even/odd banks.
 constexpr int kOutRow = 264;
+// uint16 staging of half a tile (128 rows x 256 residues) for the float
+// channels' epilogue: 528-byte rows.
+constexpr int kOutRow16 = 528;
 
-enum class Epi { kMod, kMax };
+enum class Epi { kMod, kMax, kRmw };
 
 // Band order inside one modulus: bands of kGroup tile rows, column by
 // column, so consecutive tiles share operand strips.
@@ -85,6 +90,7 @@ constexpr int kDStage = (kBM + kBN) * kDBK;          // 32 KB
 constexpr int kDLoads = (kBM + kBN) * kDBK / 1024 / 4;  // 1 KB wave loads per wave per step
 static_assert(kDLoads == 8, "load split");
 static_assert(kBM * kOutRow <= kDStages * kDStage, "output staging fits");
+static_assert(128 * kOutRow16 <= kDStages * kDStage, "float-channel staging fits");
 
 // s_waitcnt immediate: vmcnt(v) and lgkmcnt(l), expcnt untouched.
 #define OZ_WAITCNT(v, l) (((v) & 15) | (((v) >> 4) << 14) | (7 << 4) | ((l) << 8))
@@ -105,13 +111,30 @@ __device__ __forceinline__ void barrier_no_fence() {
 // residue (row stride n_pad). Modulus m with Barrett constant mu (kMod);
 // row/column maxima into gmax_a/gmax_b (kMax). `lds` holds
 // kDStages * kDStage bytes; the caller synchronizes before reusing it.
-template <Epi E>
+// Operand format of gemm_tile: INT8 (v_mfma_i32_32x32x32_i8, INT32
+// accumulators) or the float alphabets through v_mfma_f32_32x32x64_f8f6f4
+// with FP32 accumulators: FP8 E4M3 (32 bytes per lane, one instruction per
+// 64-byte K step) and FP4 E2M1 (16 bytes per lane, two per step, read as
+// INT8 is).
+enum Fmt : int { kI8 = 0, kF8 = 1, kF4 = 2 };
+
+// Epilogue of a float-channel product: residues z (uint16, row stride
+// n_pad) of the tile receive (z + lbar (W mod m)) mod m, or that value
+// alone when `first`; W = accumulator * scale (exact integers).
+struct FpEpi {
+    uint16_t* z = nullptr;
+    uint32_t lbar = 0;
+    int first = 0;
+    float scale = 1.0f;
+};
+
+template <Epi E, int F = kI8>
 __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad, int64_t n_pad,
                                           const int8_t* __restrict__ gA,
                                           const int8_t* __restrict__ gB, uint8_t* __restrict__ gZ,
                                           int32_t* __restrict__ gmax_a,
                                           int32_t* __restrict__ gmax_b, int tm, int tn,
-                                          int8_t* lds) {
+                                          int8_t* lds, FpEpi fe = FpEpi{}) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -138,11 +161,12 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
                 (lds_ptr_t)(stage + __builtin_amdgcn_readfirstlane(lds_off[p])), 16, 0, 0);
     };
 
-    v16i acc[kFM][kFN];
+    using Acc = std::conditional_t<F == kI8, v16i, v16f>;
+    Acc acc[kFM][kFN];
 #pragma unroll
     for (int a = 0; a < kFM; ++a)
 #pragma unroll
-        for (int b = 0; b < kFN; ++b) acc[a][b] = (v16i){0};
+        for (int b = 0; b < kFN; ++b) acc[a][b] = (Acc){0};
 
     // Fragment reads: row (lane & 31) of a 32-row block; logical chunk
     // 2 * kk + (lane >> 5), stored at its xor with (row >> 2) & 3, which is
@@ -153,6 +177,12 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
     const int offB = kBM * kDBK + (wj * kWaveN + fr) * kDBK;
     const int cofs0 = ((0 + (lane >> 5)) ^ fsw) * 16;
     const int cofs1 = ((2 + (lane >> 5)) ^ fsw) * 16;
+    const int nk = (int)(k_pad / kDBK);
+    const int pre = nk < 3 ? nk : 3;
+    using yes = std::integral_constant<bool, true>;
+    using no = std::integral_constant<bool, false>;
+
+    if constexpr (F != kF8) {
     v4i xa[2][kFN], yb[2][kFM];
     auto read_frags = [&](int buf, int t, int kk) {
         const int8_t* stage = lds + (t & (kDStages - 1)) * kDStage;
@@ -168,13 +198,20 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
 #pragma unroll
         for (int a = 0; a < kFM; ++a)
 #pragma unroll
-            for (int b = 0; b < kFN; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[buf][b], yb[buf][a], acc[a][b],
-                                                                  0, 0, 0);
+            for (int b = 0; b < kFN; ++b) {
+                if constexpr (F == kI8) {
+                    acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[buf][b], yb[buf][a],
+                                                                      acc[a][b], 0, 0, 0);
+                } else {
+                    const v4i x = xa[buf][b], y = yb[buf][a];
+                    const v8i x8 = {x[0], x[1], x[2], x[3], 0, 0, 0, 0};
+                    const v8i y8 = {y[0], y[1], y[2], y[3], 0, 0, 0, 0};
+                    acc[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                        x8, y8, acc[a][b], 4, 4, 0, 0, 0, 0);
+                }
+            }
     };
 
-    const int nk = (int)(k_pad / kDBK);
-    const int pre = nk < 3 ? nk : 3;
     for (int t = 0; t < pre; ++t) dma(t);
     // steps 0 and 1 in LDS (step 2 may stay in flight)
     if (nk >= 3)
@@ -222,16 +259,128 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
             __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(0, 0));
         barrier_no_fence();
     };
-    using yes = std::integral_constant<bool, true>;
-    using no = std::integral_constant<bool, false>;
     int t = 0;
     for (; t + 3 < nk; ++t) step(t, yes{}, yes{});
     for (; t + 1 < nk; ++t) step(t, no{}, yes{});
     step(t, no{}, no{});
+    } else {
+    // FP8: a fragment is 32 bytes, logical chunks 2h and 2h + 1 (h = lane >> 5).
+    // One register set per fragment: B fragment b of step t+1 is read as
+    // soon as the four MFMAs of step t that use it have issued, the A
+    // fragments after the last MFMA of the step.
+    const int c8lo = ((2 * (lane >> 5)) ^ fsw) * 16;
+    const int c8hi = ((2 * (lane >> 5) + 1) ^ fsw) * 16;
+    v8i xa[kFN], yb[kFM];
+    auto frag8 = [&](const int8_t* base) {
+        const v4i lo = *reinterpret_cast<const v4i*>(base + c8lo);
+        const v4i hi = *reinterpret_cast<const v4i*>(base + c8hi);
+        return (v8i){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    };
+    auto stage_of = [&](int t) { return lds + (t & (kDStages - 1)) * kDStage; };
+    for (int t = 0; t < pre; ++t) dma(t);
+    if (nk >= 3)
+        __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(kDLoads, 0));
+    else
+        __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(0, 0));
+    barrier_no_fence();
+#pragma unroll
+    for (int b = 0; b < kFN; ++b) xa[b] = frag8(stage_of(0) + offB + b * 32 * kDBK);
+#pragma unroll
+    for (int a = 0; a < kFM; ++a) yb[a] = frag8(stage_of(0) + offA + a * 32 * kDBK);
+    auto step8 = [&](int t, auto load_tag, auto next_tag) {
+        constexpr bool kLoad = decltype(load_tag)::value;
+        constexpr bool kNext = decltype(next_tag)::value;
+        if constexpr (kLoad) dma(t + 3);
+        const int8_t* nxt = stage_of(t + 1);
+#pragma unroll
+        for (int b = 0; b < kFN; ++b) {
+#pragma unroll
+            for (int a = 0; a < kFM; ++a)
+                acc[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                    xa[b], yb[a], acc[a][b], 0, 0, 0, 0, 0, 0);
+            if constexpr (kNext) xa[b] = frag8(nxt + offB + b * 32 * kDBK);
+        }
+        if constexpr (kNext) {
+#pragma unroll
+            for (int a = 0; a < kFM; ++a) yb[a] = frag8(nxt + offA + a * 32 * kDBK);
+        }
+        if constexpr (kLoad) {
+#pragma unroll
+            for (int i = 0; i < kDLoads; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+                __builtin_amdgcn_sched_group_barrier(0x010, 1, 0);  // global load to LDS
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (kLoad)
+            __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(kDLoads, 0));
+        else
+            __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(0, 0));
+        barrier_no_fence();
+    };
+    int t = 0;
+    for (; t + 3 < nk; ++t) step8(t, yes{}, yes{});
+    for (; t + 1 < nk; ++t) step8(t, no{}, yes{});
+    step8(t, no{}, no{});
+    }
 
     const int li = lane & 31;
     const int lj = (lane >> 5) * 4;
-    if constexpr (E == Epi::kMod) {
+    if constexpr (E == Epi::kRmw) {
+        // two passes of 128 rows: the waves of that half stage
+        // lbar (W mod m) as uint16 in LDS, then every thread adds its
+        // 16-byte pieces into the residues with coalesced reads and writes
+        uint8_t* sO = reinterpret_cast<uint8_t*>(lds);
+        for (int half = 0; half < 2; ++half) {
+            if (wi == half) {
+#pragma unroll
+                for (int a = 0; a < kFM; ++a)
+#pragma unroll
+                    for (int b = 0; b < kFN; ++b)
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) {
+                            uint32_t v[4];
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                const int32_t w = (int32_t)(acc[a][b][4 * g + q] * fe.scale);
+                                const uint32_t aw = (uint32_t)(w < 0 ? -w : w);
+                                uint32_t r = barrett32(aw, m, mu);
+                                if (w < 0 && r != 0) r = m - r;
+                                v[q] = barrett32(fe.lbar * r, m, mu);
+                            }
+                            const int i = a * 32 + li;  // row inside this half
+                            const int j = wj * kWaveN + b * 32 + 8 * g + lj;
+                            *reinterpret_cast<uint2*>(sO + i * kOutRow16 + j * 2) =
+                                make_uint2(v[0] | (v[1] << 16), v[2] | (v[3] << 16));
+                        }
+            }
+            __syncthreads();
+            uint16_t* zt = fe.z + (int64_t)(half * 128) * n_pad;
+            for (int c = tid; c < 128 * (kBN / 8); c += kThreads) {
+                const int row = c / (kBN / 8), col = (c % (kBN / 8)) * 8;
+                const uint4 add = *reinterpret_cast<const uint4*>(sO + row * kOutRow16 + col * 2);
+                uint4* dst = reinterpret_cast<uint4*>(zt + (int64_t)row * n_pad + col);
+                if (fe.first) {
+                    *dst = add;
+                } else {
+                    const uint4 old = *dst;
+                    const uint32_t* pa = reinterpret_cast<const uint32_t*>(&add);
+                    const uint32_t* po = reinterpret_cast<const uint32_t*>(&old);
+                    uint32_t o[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        uint32_t lo = (pa[q] & 0xFFFFu) + (po[q] & 0xFFFFu);
+                        uint32_t hi = (pa[q] >> 16) + (po[q] >> 16);
+                        lo -= (lo >= m) ? m : 0u;
+                        hi -= (hi >= m) ? m : 0u;
+                        o[q] = lo | (hi << 16);
+                    }
+                    *dst = make_uint4(o[0], o[1], o[2], o[3]);
+                }
+            }
+            __syncthreads();
+        }
+    } else if constexpr (E == Epi::kMod) {
         uint8_t* sO = reinterpret_cast<uint8_t*>(lds);
 #pragma unroll
         for (int a = 0; a < kFM; ++a) {
@@ -312,6 +461,40 @@ __global__ __launch_bounds__(kThreads) void residue_gemm_kernel(ModConsts mc, in
                  gB, gZ, gmax_a, gmax_b, tm, tn, lds);
 }
 
+// Float-channel products of one plane round over one slab: work item b
+// is a tile of channel item c (start[c] <= b < start[c + 1]), A plane
+// plane[c] times B plane plane[c] over K bytes [kb_begin, kb_begin + kb_len),
+// epilogue into the residues of channel chan[c] with weight lbar[c].
+template <int F>
+__global__ __launch_bounds__(kThreads) void fp_gemm_kernel(FpGemmArgs g) {
+    __shared__ __align__(1024) int8_t lds[kDStages * kDStage];
+    const int64_t bid = blockIdx.x;
+    int c = 0;
+    while (c + 1 < g.count && bid >= g.start[c + 1]) ++c;
+    const int tiles_m = (int)(g.m_pad / kBM), tiles_n = (int)(g.n_pad / kBN);
+    const int64_t T = (int64_t)tiles_m * tiles_n;
+    const int64_t local = bid - g.start[c];
+    // XCD-aware: workgroup b runs on XCD b % 8; give each XCD a contiguous
+    // eighth of the channel's tiles in band order when the start allows
+    int64_t t = local;
+    if ((T & 7) == 0 && (g.start[c] & 7) == 0) t = (local & 7) * (T >> 3) + (local >> 3);
+    int tm, tn;
+    band_tile(t, tiles_m, tiles_n, tm, tn);
+    const int64_t pl = g.plane[c];
+    const int8_t* gA = g.pa + pl * g.m_pad * g.kb_pad + (int64_t)tm * kBM * g.kb_pad +
+                       (g.kb_begin / kDBK) * (kPlaneRows * kPlaneK);
+    const int8_t* gB = g.pb + pl * g.n_pad * g.kb_pad + (int64_t)tn * kBN * g.kb_pad +
+                       (g.kb_begin / kDBK) * (kPlaneRows * kPlaneK);
+    FpEpi fe;
+    fe.z = g.z + (int64_t)g.chan[c] * g.m_pad * g.n_pad + (int64_t)tm * kBM * g.n_pad +
+           (int64_t)tn * kBN;
+    fe.lbar = g.lbar[c];
+    fe.first = g.first;
+    fe.scale = g.scale;
+    gemm_tile<Epi::kRmw, F>(g.m[c], g.mu[c], g.kb_len, g.n_pad, gA, gB, nullptr, nullptr, nullptr,
+                            tm, tn, lds, fe);
+}
+
 // Grouped residue GEMM, persistent: workgroup b starts on the list of its
 // XCD (b % 8, the hardware's round-robin placement) and takes work items
 // (problem, modulus, tile) from that list's counter; when it is exhausted
@@ -363,6 +546,16 @@ hipError_t launch_group_gemm(hipStream_t st, const GroupArgs& g, const int32_t* 
     if (tiles <= 0) return hipSuccess;
     const int32_t grid = workers < tiles ? workers : (int32_t)tiles;
     group_gemm_kernel<<<dim3((unsigned)grid), dim3(kThreads), 0, st>>>(g);
+    return hipGetLastError();
+}
+
+hipError_t launch_fp_gemm(hipStream_t st, const FpGemmArgs& g, int fmt) {
+    const int64_t blocks = g.start[g.count];
+    if (blocks <= 0) return hipSuccess;
+    if (fmt == 4)
+        fp_gemm_kernel<kF4><<<dim3((unsigned)blocks), dim3(kThreads), 0, st>>>(g);
+    else
+        fp_gemm_kernel<kF8><<<dim3((unsigned)blocks), dim3(kThreads), 0, st>>>(g);
     return hipGetLastError();
 }
 

@@ -201,6 +201,43 @@ __host__ __device__ __forceinline__ uint32_t trunc_residue(uint64_t mant, int sh
     return barrett32(r0 * pow2mod(sh, m, mu), m, mu);
 }
 
+// Limb channels of a float alphabet (FP8 E4M3, FP4 E2M1) for the kernels:
+// channel c has modulus m[c], rank[c] planes (1: one limb; 3: two-limb Toom
+// form at points 0, 1, infinity) starting at plane plane0[c], weights
+// lbar[c][k] (the form's weights reduced into [0, m)), the 12-bit digit
+// weights 2^(12 i) mod m, and its code table at byte toff[c] of the table
+// blob: m * rank bytes, the format codes of the plane values of each class.
+struct FpConsts {
+    int n;       // channels
+    int planes;  // sum of ranks
+    int fmt;     // MFMA operand format: 0 FP8 E4M3, 4 FP4 E2M1
+    int es;      // plane value v is stored as v * 2^-es
+    uint32_t m[kMaxModuli];
+    uint32_t mu[kMaxModuli];
+    int32_t rank[kMaxModuli];
+    int32_t plane0[kMaxModuli];
+    int32_t toff[kMaxModuli];
+    uint32_t lbar[kMaxModuli][3];
+    uint16_t w12[kMaxModuli][6];
+};
+
+// One plane round of the float-channel products over one slab (kernel
+// argument): items c < count, each tiles of one channel's plane; K bytes
+// [kb_begin, kb_begin + kb_len) of planes whose rows hold kb_pad bytes.
+struct FpGemmArgs {
+    int count;
+    int first;        // the residues start at zero (first plane of the first slab)
+    float scale;      // 2^(2 es): accumulator to integer
+    int64_t start[kMaxModuli + 1];  // first workgroup of each item
+    int32_t plane[kMaxModuli];
+    int32_t chan[kMaxModuli];
+    uint32_t m[kMaxModuli], mu[kMaxModuli], lbar[kMaxModuli];
+    int64_t m_pad, n_pad, kb_pad, kb_begin, kb_len;
+    const int8_t* pa;
+    const int8_t* pb;
+    uint16_t* z;
+};
+
 // ---- Grouped launches: many independent products in one set of launches.
 // The work of each phase is a list of workgroups, problem after problem:
 // prefix[kind * (count + 1) + p] is the first workgroup of problem p and
@@ -314,6 +351,19 @@ hipError_t launch_reconstruct(hipStream_t st, const CrtConsts& cc, int64_t m, in
                               const int32_t* shift_a, const int32_t* shift_b, double* C,
                               int64_t ldc);
 hipError_t launch_zero_c(hipStream_t st, int64_t m, int64_t n, double* C, int64_t ldc);
+
+// Float channels: Reduce (codes of every plane), one plane round of the
+// residue GEMMs, Reconstruct from uint16 residues.
+hipError_t launch_encode_fp(hipStream_t st, const FpConsts& fc, const uint8_t* tables,
+                            int table_bytes, int64_t m, int64_t n, int64_t k, const double* A,
+                            int64_t lda, const double* B, int64_t ldb, const int32_t* shift_a,
+                            const int32_t* shift_b, int64_t m_pad, int64_t n_pad, int64_t k_pad,
+                            int8_t* planes_a, int8_t* planes_b);
+hipError_t launch_fp_gemm(hipStream_t st, const FpGemmArgs& g, int fmt);
+hipError_t launch_reconstruct16(hipStream_t st, const CrtConsts& cc, int64_t m, int64_t n,
+                                int64_t m_pad, int64_t n_pad, const uint16_t* residues,
+                                const int32_t* shift_a, const int32_t* shift_b, double* C,
+                                int64_t ldc);
 
 // Grouped phases; `total` is the phase's workgroup count (prefix total).
 hipError_t launch_group_init(hipStream_t st, const GroupArgs& g, int32_t total);

@@ -28,6 +28,11 @@ struct BigU {
     double log2() const;
 };
 
+// One limb channel: modulus, rank (1 one-limb, 3 two-limb Toom), base.
+struct FpChannel {
+    int m = 0, rank = 0, base = 0;
+};
+
 struct Plan {
     int format = 0;
     int scaling = 0;
@@ -38,7 +43,20 @@ struct Plan {
     int64_t kappa_acc = 0;    // Lambda_INT32 / max radius^2
     ModConsts mod{};
     CrtConsts crt{};
+    // float-alphabet plans (format != 0)
+    int64_t k_slab = 0;                 // terms per accumulation slab
+    std::vector<FpChannel> chans;
+    FpConsts fp{};
+    std::vector<uint8_t> tables;        // code tables of all channels
+    uint8_t* pinned_tables = nullptr;   // pinned copy for uploads (first call)
 };
+
+// Float-alphabet plan (format 1 E4M3, 3 E2M1): the channel pool at slab
+// length k_slab (one-limb and two-limb Toom channels within the radius
+// floor(sqrt(2^24 / k_slab))), then the coprime selection: within `gemms`
+// GEMMs the largest product, or for gemms == 0 the least GEMM count whose
+// product exceeds k_slab * 2^107. Builds the code tables and constants.
+std::string build_plan_fp(Plan& p, int format, int gemms, int64_t k_slab, int scaling);
 
 // Largest-product pairwise-coprime set of `count` integers in [2, limit]
 // (ties: lexicographically largest descending list). Empty on failure.

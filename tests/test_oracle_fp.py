@@ -45,6 +45,16 @@ def test_e4m3_least_q_at_2_12_matches_paper():
     assert sum(mb.rank for mb in cfg) == 29
 
 
+def test_e2m1_least_q_at_2_14_between_paper_and_ozii_fp4():
+    """With one-limb and two-limb Toom forms only, E2M1 reaches the window
+    at K = 2**14 in 62 GEMMs: no fewer than the paper's 59 over its larger
+    pool, fewer than OzII-FP4's 75 (Table "moduli")."""
+    cfg = fc.configuration("E2M1", 2 ** 14, window_k=2 ** 14)
+    q = sum(mb.rank for mb in cfg)
+    assert q == 62 and 59 <= q < 75
+    assert fc.pairwise_coprime(cfg)
+
+
 def test_e2m3_takes_e4m3_configuration_at_2_14(e4m3_14):
     assert fc.configuration("E2M3", 2 ** 14, window_k=2 ** 14) == e4m3_14
 
