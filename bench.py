@@ -42,7 +42,12 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=32,
                     help="rows of C in the CPU oracle's bounded sample")
     ap.add_argument("--no-native", action="store_true")
-    ap.add_argument("--workload", default="dgemm", choices=["dgemm", "mlp", "grouped"],
+    ap.add_argument("--format", default="E4M3", choices=["E4M3", "E2M1"],
+                    help="fp workload: float alphabet of the limb channels")
+    ap.add_argument("--gemms-list", default="0",
+                    help="fp workload: comma-separated GEMM counts (0: least count for the "
+                         "window at K = 16384)")
+    ap.add_argument("--workload", default="dgemm", choices=["dgemm", "mlp", "grouped", "fp"],
                     help="dgemm: the 8192^3 emulated DGEMM (default); mlp: one training "
                          "step of a 4-layer tanh MLP through the cached-residue backward; "
                          "grouped: 512 uneven products as one grouped run in a HIP graph")
@@ -264,6 +269,68 @@ def grouped_main(args):
     print(json.dumps(out), flush=True)
 
 
+def fp_main(args):
+    """FP64 products through FP8 E4M3 / FP4 E2M1 limb channels (FP32
+    accumulation, slabs of 16384 terms) at m = n = k = size (16384 unless
+    --size is given), phi = 1: one whole emulated call per step for every
+    GEMM count in --gemms-list, with the exact scaled error on 64 sampled
+    entries and the relative Frobenius difference from native FP64."""
+    import torch
+    import paper_2609_37693_amd as oz
+    from oracle import exact
+    from workloads import operand_pair
+
+    n = args.size if args.size != 8192 else 16384
+    A_h, B_h = operand_pair(n, n, n, 1.0, args.seed)
+    A = torch.from_numpy(A_h).cuda()
+    B = torch.from_numpy(B_h).cuda()
+    ref = A @ B
+    native_ms = time_stream(lambda: torch.matmul(A, B, out=ref), max(3, args.steps // 2), 1)
+    rng = np.random.default_rng(3)
+    rows = np.sort(rng.choice(n, 8, replace=False))
+    cols = np.sort(rng.choice(n, 8, replace=False))
+    As = np.ascontiguousarray(A_h[rows])
+    Bs = np.ascontiguousarray(B_h[:, cols])
+    flops = 2.0 * n ** 3
+    peak = 5000.0 if args.format == "E4M3" else 10100.0
+    curve = []
+    for g in [int(x) for x in args.gemms_list.split(",")]:
+        plan = oz.Plan(format=args.format, gemms=g, k_slab=16384)
+        C = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        ws = torch.empty(plan.workspace_size(n, n, n), dtype=torch.uint8, device="cuda")
+        ms = time_stream(lambda: oz.dgemm(A, B, plan, out=C, workspace=ws), args.steps,
+                         args.warmup)
+        torch.cuda.synchronize()
+        Q = plan.gemms()
+        got = C[torch.from_numpy(rows).cuda()][:, torch.from_numpy(cols).cuda()].cpu().numpy()
+        err = exact.scaled_error(got, As, Bs)
+        rel = float(torch.linalg.norm(C - ref) / torch.linalg.norm(ref))
+        curve.append({"gemms": Q, "channels": len(plan.channels()),
+                      "kept_bits": list(plan.kept_bits(n)), "ms": ms,
+                      "tflops": flops / (ms * 1e-3) / 1e12,
+                      "lowp_tflops": 2.0 * Q * n ** 3 / (ms * 1e-3) / 1e12,
+                      "scaled_error_sample": err, "rel_frobenius_vs_native": rel,
+                      "speedup_vs_native": native_ms / ms})
+        del C, ws
+        torch.cuda.empty_cache()
+    head = curve[0]
+    out = {
+        "metric": "emulated DGEMM TFLOP/s through %s limb channels at %d^3" % (args.format, n),
+        "value": head["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp8" if args.format == "E4M3" else "fp4", "data": "synthetic",
+        "config": {"workload": "emulated DGEMM m=n=k=%d, phi = 1, %s channels, FP32 "
+                               "accumulation, slabs of 16384" % (n, args.format),
+                   "format": args.format, "gemms": head["gemms"]},
+        "roofline_whole_call": {"bound": "mfma", "achieved": head["lowp_tflops"], "peak": peak,
+                                "unit": "TFLOP/s", "frac": head["lowp_tflops"] / peak},
+        "native_fp64": {"ms": native_ms, "value": flops / (native_ms * 1e-3) / 1e12},
+        "curve": curve,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -275,7 +342,7 @@ def main():
         if not torch.cuda.is_available():
             print("no HIP device", file=sys.stderr)
             sys.exit(1)
-        return mlp_main(args) if args.workload == "mlp" else grouped_main(args)
+        return {"mlp": mlp_main, "grouped": grouped_main, "fp": fp_main}[args.workload](args)
     import paper_2609_37693_amd as oz
     from workloads import operand_pair
 
