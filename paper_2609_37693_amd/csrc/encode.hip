@@ -18,11 +18,11 @@ constexpr int kEncVec = 16;   // consecutive k entries per thread (one 16-byte s
 constexpr int kMaxShift = 80; // largest left shift of a significand: kBetaCap - 53 < 80
 
 // One entry, prepared once for all moduli. With kBig false the kept bits
-// are at most 63 and |A'| = mant 2^sh (or mant >> -sh) fits in 64 bits:
-// its 12-bit digits are stored. With kBig true only mant's digits are stored
-// and a positive shift is applied per modulus as a factor 2^sh mod m.
+// are at most 63 and |A'| = mant 2^sh (or mant >> -sh) fits in 64 bits,
+// stored as two 32-bit words. With kBig true only mant is stored and a
+// positive shift is applied per modulus as a factor 2^sh mod m.
 struct Entry {
-    Digits12 g;
+    uint32_t lo, hi;
     int sh;    // > 0 only in the kBig form
     bool neg;
 };
@@ -51,7 +51,8 @@ __device__ __forceinline__ Entry make_entry(double x, int32_t shift) {
     } else {
         v = mant;
     }
-    e.g = digits12(v);
+    e.lo = (uint32_t)v;
+    e.hi = (uint32_t)(v >> 32);
     e.sh = sh;
     return e;
 }
@@ -63,7 +64,11 @@ __device__ __forceinline__ int8_t entry_residue(const Entry& e, const ModConsts&
                                                 const uint8_t* p2) {
     const uint32_t m = mc.m[l];
     const float rcp = mc.rcp[l];
-    uint32_t r = digits_mod(e.g, mc.w12[l], m, rcp);
+    // sum of the eight bytes of |A'| times 2^(8 i) mod m: below 2^20, so the
+    // FP32-reciprocal reduction is exact
+    uint32_t t = __builtin_amdgcn_udot4(e.lo, mc.w8[l][0], 0u, false);
+    t = __builtin_amdgcn_udot4(e.hi, mc.w8[l][1], t, false);
+    uint32_t r = mod24(t, m, rcp);
     if (kBig && e.sh > 0) r = mod24(r * p2[e.sh], m, rcp);
     if (e.neg) r = r ? m - r : 0;
     const int32_t v = (r >= (m + 1) / 2) ? (int32_t)r - (int32_t)m : (int32_t)r;
@@ -251,6 +256,7 @@ __global__ __launch_bounds__(kEncThreads) void encode_b_kernel(ModConsts mc, int
 
 __device__ __forceinline__ uint32_t fp_class(const Digits12& g, bool neg, const FpConsts& fc,
                                              int c) {
+    // 12-bit digits: float-channel moduli exceed a byte
     const uint16_t* w = fc.w12[c];
     uint32_t t = g.d[0];
     t = __umul24(g.d[1], w[1]) + t;
@@ -325,10 +331,13 @@ __global__ __launch_bounds__(kEncThreads) void encode_fp_a_kernel(
         const bool in = h + q < k;
         ent[q] = make_entry<false>(in ? row[h + q] : 0.0, in ? s : 0);
     }
+    Digits12 g[kEncVec];
+#pragma unroll
+    for (int q = 0; q < kEncVec; ++q) g[q] = digits12(((uint64_t)ent[q].hi << 32) | ent[q].lo);
     for (int ch = 0; ch < fc.n; ++ch) {
         uint32_t cls[kEncVec];
 #pragma unroll
-        for (int q = 0; q < kEncVec; ++q) cls[q] = fp_class(ent[q].g, ent[q].neg, fc, ch);
+        for (int q = 0; q < kEncVec; ++q) cls[q] = fp_class(g[q], ent[q].neg, fc, ch);
         const int rank = fc.rank[ch];
         const uint8_t* t = tab + fc.toff[ch];
         for (int r = 0; r < rank; ++r) {
@@ -364,10 +373,13 @@ __global__ __launch_bounds__(kEncThreads) void encode_fp_b_kernel(
         const bool in = h + q < k;
         ent[q] = make_entry<false>(in ? B[(h + q) * ldb + j] : 0.0, in ? s : 0);
     }
+    Digits12 g[kEncVec];
+#pragma unroll
+    for (int q = 0; q < kEncVec; ++q) g[q] = digits12(((uint64_t)ent[q].hi << 32) | ent[q].lo);
     for (int ch = 0; ch < fc.n; ++ch) {
         uint32_t cls[kEncVec];
 #pragma unroll
-        for (int q = 0; q < kEncVec; ++q) cls[q] = fp_class(ent[q].g, ent[q].neg, fc, ch);
+        for (int q = 0; q < kEncVec; ++q) cls[q] = fp_class(g[q], ent[q].neg, fc, ch);
         const int rank = fc.rank[ch];
         const uint8_t* t = tab + fc.toff[ch];
         for (int r = 0; r < rank; ++r) {

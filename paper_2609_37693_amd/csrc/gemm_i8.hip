@@ -85,7 +85,10 @@ __device__ __forceinline__ void tile_of(int64_t bid, int tiles_m, int tiles_n, i
 // across it. MFMA operands are read one 32-byte slice ahead, across step
 // boundaries.
 constexpr int kDBK = 64;
+// Ring depth: four K steps (128 KiB). A fifth (the 160 KiB limit) measured
+// slower at 8192^3, so every kernel uses four.
 constexpr int kDStages = 4;
+constexpr int kDStagesMax = 5;
 constexpr int kDStage = (kBM + kBN) * kDBK;          // 32 KB
 constexpr int kDLoads = (kBM + kBN) * kDBK / 1024 / 4;  // 1 KB wave loads per wave per step
 static_assert(kDLoads == 8, "load split");
@@ -110,7 +113,8 @@ __device__ __forceinline__ void barrier_no_fence() {
 // and B planes of one modulus (plane_offset order), gZ at the tile's first
 // residue (row stride n_pad). Modulus m with Barrett constant mu (kMod);
 // row/column maxima into gmax_a/gmax_b (kMax). `lds` holds
-// kDStages * kDStage bytes; the caller synchronizes before reusing it.
+// S * kDStage bytes (a ring of S K steps, loads issued S - 1 steps ahead);
+// the caller synchronizes before reusing it.
 // Operand format of gemm_tile: INT8 (v_mfma_i32_32x32x32_i8, INT32
 // accumulators) or the float alphabets through v_mfma_f32_32x32x64_f8f6f4
 // with FP32 accumulators: FP8 E4M3 (32 bytes per lane, one instruction per
@@ -128,7 +132,7 @@ struct FpEpi {
     float scale = 1.0f;
 };
 
-template <Epi E, int F = kI8>
+template <Epi E, int F = kI8, int S = kDStages>
 __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad, int64_t n_pad,
                                           const int8_t* __restrict__ gA,
                                           const int8_t* __restrict__ gB, uint8_t* __restrict__ gZ,
@@ -140,6 +144,13 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
     const int wave = tid >> 6;
     const int wi = wave >> 1;
     const int wj = wave & 1;
+    static_assert(S >= 4 && S <= kDStagesMax, "ring depth");
+    auto ring = [](int t) {
+        if constexpr ((S & (S - 1)) == 0)
+            return t & (S - 1);
+        else
+            return (int)((unsigned)t % (unsigned)S);
+    };
 
     // Loads: wave-load R = wave * 8 + p copies kilobyte R % 16 of operand
     // R / 16's block for the step; lane L moves bytes [16 L, 16 L + 16).
@@ -153,7 +164,7 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
         lds_off[p] = side * kBM * kDBK + r16 * 1024;
     }
     auto dma = [&](int t) {
-        int8_t* stage = lds + (t & (kDStages - 1)) * kDStage;
+        int8_t* stage = lds + ring(t) * kDStage;
 #pragma unroll
         for (int p = 0; p < kDLoads; ++p)
             __builtin_amdgcn_global_load_lds(
@@ -178,14 +189,31 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
     const int cofs0 = ((0 + (lane >> 5)) ^ fsw) * 16;
     const int cofs1 = ((2 + (lane >> 5)) ^ fsw) * 16;
     const int nk = (int)(k_pad / kDBK);
-    const int pre = nk < 3 ? nk : 3;
+    const int pre = nk < S - 1 ? nk : S - 1;
+    // waits: at the end of step t stage t + 2 must be in LDS; the loads of
+    // the stages issued after it may stay in flight
+    auto wait_prologue = [&]() {
+        if (pre >= 4)
+            __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(2 * kDLoads, 0));
+        else if (pre == 3)
+            __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(kDLoads, 0));
+        else
+            __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(0, 0));
+    };
+    auto wait_stages = [&](auto n_tag) {
+        constexpr int n = decltype(n_tag)::value;
+        __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(n * kDLoads, 0));
+    };
+    using w0 = std::integral_constant<int, 0>;
+    using w1 = std::integral_constant<int, 1>;
+    using wL = std::integral_constant<int, S - 3>;
     using yes = std::integral_constant<bool, true>;
     using no = std::integral_constant<bool, false>;
 
     if constexpr (F != kF8) {
     v4i xa[2][kFN], yb[2][kFM];
     auto read_frags = [&](int buf, int t, int kk) {
-        const int8_t* stage = lds + (t & (kDStages - 1)) * kDStage;
+        const int8_t* stage = lds + ring(t) * kDStage;
         const int c = kk ? cofs1 : cofs0;
 #pragma unroll
         for (int b = 0; b < kFN; ++b)
@@ -214,20 +242,17 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
 
     for (int t = 0; t < pre; ++t) dma(t);
     // steps 0 and 1 in LDS (step 2 may stay in flight)
-    if (nk >= 3)
-        __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(kDLoads, 0));
-    else
-        __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(0, 0));
+    wait_prologue();
     barrier_no_fence();
     read_frags(0, 0, 0);
 
     // One step: kLoad issues the loads of step t+3; kNext reads the first
     // operands of step t+1 during the second slice. Ends with the wait for
     // step t+2's loads and the barrier that publishes them.
-    auto step = [&](int t, auto load_tag, auto next_tag) {
+    auto step = [&](int t, auto load_tag, auto next_tag, auto wait_tag) {
         constexpr bool kLoad = decltype(load_tag)::value;
         constexpr bool kNext = decltype(next_tag)::value;
-        if constexpr (kLoad) dma(t + 3);
+        if constexpr (kLoad) dma(t + S - 1);
         read_frags(1, t, 1);
         mfma_slice(0);
         if constexpr (kLoad) {
@@ -253,16 +278,17 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
             }
         }
         __builtin_amdgcn_sched_barrier(0);
-        if constexpr (kLoad)
-            __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(kDLoads, 0));
-        else
-            __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(0, 0));
+        wait_stages(wait_tag);
         barrier_no_fence();
     };
     int t = 0;
-    for (; t + 3 < nk; ++t) step(t, yes{}, yes{});
-    for (; t + 1 < nk; ++t) step(t, no{}, yes{});
-    step(t, no{}, no{});
+    for (; t + S - 1 < nk; ++t) step(t, yes{}, yes{}, wL{});
+    if (S == 5 && t + 4 == nk) {  // stage t + 3 = nk - 1 may stay in flight
+        step(t, no{}, yes{}, w1{});
+        ++t;
+    }
+    for (; t + 1 < nk; ++t) step(t, no{}, yes{}, w0{});
+    step(t, no{}, no{}, w0{});
     } else {
     // FP8: a fragment is 32 bytes, logical chunks 2h and 2h + 1 (h = lane >> 5).
     // One register set per fragment: B fragment b of step t+1 is read as
@@ -276,21 +302,18 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
         const v4i hi = *reinterpret_cast<const v4i*>(base + c8hi);
         return (v8i){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
     };
-    auto stage_of = [&](int t) { return lds + (t & (kDStages - 1)) * kDStage; };
+    auto stage_of = [&](int t) { return lds + ring(t) * kDStage; };
     for (int t = 0; t < pre; ++t) dma(t);
-    if (nk >= 3)
-        __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(kDLoads, 0));
-    else
-        __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(0, 0));
+    wait_prologue();
     barrier_no_fence();
 #pragma unroll
     for (int b = 0; b < kFN; ++b) xa[b] = frag8(stage_of(0) + offB + b * 32 * kDBK);
 #pragma unroll
     for (int a = 0; a < kFM; ++a) yb[a] = frag8(stage_of(0) + offA + a * 32 * kDBK);
-    auto step8 = [&](int t, auto load_tag, auto next_tag) {
+    auto step8 = [&](int t, auto load_tag, auto next_tag, auto wait_tag) {
         constexpr bool kLoad = decltype(load_tag)::value;
         constexpr bool kNext = decltype(next_tag)::value;
-        if constexpr (kLoad) dma(t + 3);
+        if constexpr (kLoad) dma(t + S - 1);
         const int8_t* nxt = stage_of(t + 1);
 #pragma unroll
         for (int b = 0; b < kFN; ++b) {
@@ -312,16 +335,17 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
             }
         }
         __builtin_amdgcn_sched_barrier(0);
-        if constexpr (kLoad)
-            __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(kDLoads, 0));
-        else
-            __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(0, 0));
+        wait_stages(wait_tag);
         barrier_no_fence();
     };
     int t = 0;
-    for (; t + 3 < nk; ++t) step8(t, yes{}, yes{});
-    for (; t + 1 < nk; ++t) step8(t, no{}, yes{});
-    step8(t, no{}, no{});
+    for (; t + S - 1 < nk; ++t) step8(t, yes{}, yes{}, wL{});
+    if (S == 5 && t + 4 == nk) {
+        step8(t, no{}, yes{}, w1{});
+        ++t;
+    }
+    for (; t + 1 < nk; ++t) step8(t, no{}, yes{}, w0{});
+    step8(t, no{}, no{}, w0{});
     }
 
     const int li = lane & 31;
@@ -457,8 +481,8 @@ __global__ __launch_bounds__(kThreads) void residue_gemm_kernel(ModConsts mc, in
     uint8_t* gZ = (E == Epi::kMod)
                       ? Z + (int64_t)l * plane_z + (int64_t)tm * kBM * n_pad + (int64_t)tn * kBN
                       : nullptr;
-    gemm_tile<E>(E == Epi::kMod ? mc.m[l] : 0u, E == Epi::kMod ? mc.mu[l] : 0u, k_pad, n_pad, gA,
-                 gB, gZ, gmax_a, gmax_b, tm, tn, lds);
+    gemm_tile<E, kI8, kDStages>(E == Epi::kMod ? mc.m[l] : 0u, E == Epi::kMod ? mc.mu[l] : 0u,
+                                   k_pad, n_pad, gA, gB, gZ, gmax_a, gmax_b, tm, tn, lds);
 }
 
 // Float-channel products of one plane round over one slab: work item b
@@ -491,8 +515,8 @@ __global__ __launch_bounds__(kThreads) void fp_gemm_kernel(FpGemmArgs g) {
     fe.lbar = g.lbar[c];
     fe.first = g.first;
     fe.scale = g.scale;
-    gemm_tile<Epi::kRmw, F>(g.m[c], g.mu[c], g.kb_len, g.n_pad, gA, gB, nullptr, nullptr, nullptr,
-                            tm, tn, lds, fe);
+    gemm_tile<Epi::kRmw, F, kDStages>(g.m[c], g.mu[c], g.kb_len, g.n_pad, gA, gB, nullptr,
+                                         nullptr, nullptr, tm, tn, lds, fe);
 }
 
 // Grouped residue GEMM, persistent: workgroup b starts on the list of its

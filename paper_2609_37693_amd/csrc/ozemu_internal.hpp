@@ -48,6 +48,7 @@ struct ModConsts {
     uint32_t c16[kMaxModuli];  // 2^16 mod m
     float rcp[kMaxModuli];     // 1 / m rounded to FP32
     uint16_t w12[kMaxModuli][6];  // 2^(12 i) mod m, i = 0..5
+    uint32_t w8[kMaxModuli][2];   // bytes 2^(8 i) mod m, i = 0..3 and 4..7 (m <= 256)
 };
 
 // t mod m for t < 2^24 and 2 <= m <= 256: t is exact in FP32 and t * rcp

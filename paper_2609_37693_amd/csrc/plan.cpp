@@ -232,6 +232,13 @@ std::string fill_moduli(Plan& p, const std::vector<int>& ms) {
             for (int b = 0; b < 12 * i; ++b) w = (w * 2) % m;
             p.mod.w12[l][i] = (uint16_t)w;
         }
+        p.mod.w8[l][0] = p.mod.w8[l][1] = 0;
+        if (m <= 256)
+            for (int i = 0; i < 8; ++i) {
+                uint64_t w = 1 % m;
+                for (int b = 0; b < 8 * i; ++b) w = (w * 2) % m;
+                p.mod.w8[l][i / 4] |= (uint32_t)w << (8 * (i % 4));
+            }
         p.crt.m[l] = m;
         p.crt.mu[l] = mu;
         p.crt.rcp[l] = 1.0 / (double)m;
