@@ -154,11 +154,15 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
 
     // Loads: wave-load R = wave * 8 + p copies kilobyte R % 16 of operand
     // R / 16's block for the step; lane L moves bytes [16 L, 16 L + 16).
+    // The LDS destination of a wave-level load is uniform: its offsets are
+    // made scalar once, outside the K loop, so each load's M0 comes from
+    // scalar arithmetic only.
     const int8_t* gsrc[kDLoads];
     int lds_off[kDLoads];
+    const int wave_s = __builtin_amdgcn_readfirstlane(wave);
 #pragma unroll
     for (int p = 0; p < kDLoads; ++p) {
-        const int R = wave * kDLoads + p;
+        const int R = wave_s * kDLoads + p;
         const int side = R >> 4, r16 = R & 15;
         gsrc[p] = (side ? gB : gA) + r16 * 1024 + lane * 16;
         lds_off[p] = side * kBM * kDBK + r16 * 1024;
@@ -169,7 +173,7 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
         for (int p = 0; p < kDLoads; ++p)
             __builtin_amdgcn_global_load_lds(
                 (const void*)(gsrc[p] + (int64_t)t * (kPlaneRows * kPlaneK)),
-                (lds_ptr_t)(stage + __builtin_amdgcn_readfirstlane(lds_off[p])), 16, 0, 0);
+                (lds_ptr_t)(stage + lds_off[p]), 16, 0, 0);
     };
 
     using Acc = std::conditional_t<F == kI8, v16i, v16f>;

@@ -247,3 +247,20 @@ def test_full_size_sampled_parity_and_error():
     assert np.array_equal(Cs, ref)
     err = exact.scaled_error(Cs, As, Bs)
     assert err <= 2.0 ** -50, err
+
+
+@pytest.mark.parametrize("shape,mode,nmod", [((4100, 300, 200), "W", 14), ((6000, 50, 70), "G", 16),
+                                             ((4352, 257, 129), "F53", 16)])
+def test_tall_products_match_oracle(shape, mode, nmod):
+    """Tall products (more than 4096 rows, a ragged last tile row) in modes
+    W, G and F53: bitwise equal to the oracle, and repeated calls agree."""
+    import torch
+    m, n, k = shape
+    A, B = _inputs(m, n, k, 1.0, 31)
+    plan = oz.Plan(num_moduli=nmod, scaling=mode)
+    C1 = oz.dgemm(dev(A), dev(B), plan)
+    C2 = oz.dgemm(dev(A), dev(B), plan)
+    torch.cuda.synchronize()
+    ref = scheme.emulate(A, B, plan.moduli(), mode, blas=True, keep=False)["C"]
+    assert np.array_equal(host(C1), ref)
+    assert np.array_equal(host(C2), ref)
