@@ -2,16 +2,18 @@
 // entry, the balanced CRT solution X of its residues, then one rounding of
 // X 2^-(s_i + t_j) into FP64.
 //
-// CRT sum in digits whose sums stay exact: with u_l = (z_l inv_l) mod m_l,
-// S = sum_l u_l M_l is accumulated per 32-bit digit in 64-bit integers (each
-// term below 2^40, at most 32 terms). S / P = sum_l u_l / m_l exactly, so one
-// FP64 estimate q = rint(sum_l u_l / m_l) of the nearest multiple of P gives
-// X = S - q P, exact in the same digits. When the estimate is off by one
-// (only possible when |X| is within a few ulps of P / 2), |X| exceeds
-// (P - 1) / 2 and the exact fallback replaces |X| by P - |X| with the sign
-// flipped. The magnitude is then rounded once, to nearest even, at the bit
-// that lands on 2^-1074 or on the 53rd significant bit, whichever is higher,
-// and scaled by an exact ldexp; overflow gives an infinity.
+// CRT sum in digits whose sums stay exact. With INT8 moduli the residues
+// z_l enter directly: S = sum_l z_l N_l with N_l = inv_l M_l (below P,
+// inv_l = M_l^-1 mod m_l) is congruent to X modulo P and S / P = sum_l z_l
+// inv_l / m_l exactly. With float-channel moduli u_l = (z_l inv_l) mod m_l
+// comes first and S = sum_l u_l M_l. Either way one FP64 estimate q of the
+// nearest integer to S / P gives X = S - q P, exact in the same digits. When
+// the estimate is off by one (only possible when |X| is within a few ulps of
+// P / 2), |X| exceeds (P - 1) / 2 and the exact fallback replaces |X| by
+// P - |X| with the sign flipped. The magnitude is then rounded once, to
+// nearest even, at the bit that lands on 2^-1074 or on the 53rd significant
+// bit, whichever is higher, and scaled by an exact ldexp; overflow gives an
+// infinity.
 #include "ozemu_internal.hpp"
 
 namespace ozemu {
@@ -99,6 +101,100 @@ __device__ __forceinline__ double finish_one(const CrtConsts& cc, int64_t* acc, 
     return neg ? -r : r;
 }
 
+// Finishes one entry from its CRT sum S = sum_l z_l N_l held as KC
+// FP64 chunks s_k (S = sum_k s_k 2^(40 k), each s_k an integer below
+// 2^53) with INT8 moduli. Branch-free: q = rint(sum_k s_k 2^(40 k) / P)
+// (within 2^-30 of S / P); X = S - q P chunk by chunk, exact, then carried
+// into 40-bit chunks in [0, 2^40) whose last carry (-1 or 0) is the sign;
+// the chunks give the 32-bit words of X, two's complement, then of |X|
+// (fallback as in finish_one). The rounding position is
+// rb = max(L - 53, sc - 1074) for the bit length L of |X|: the 64 bits of
+// |X| from p = max(rb - 2, 0) up, the bits below p folded into the lowest
+// (they are only a sticky bit), are rounded at rb to nearest even in
+// integer arithmetic and scaled exactly.
+template <int D, int KC>
+__device__ __forceinline__ double finish_chunks(const CrtConsts& cc, const double* s, int sc) {
+    double f = 0.0;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) f = __builtin_fma(s[k], cc.R40[k], f);
+    const double q = rint(f);
+    uint64_t ch[KC + 1];
+    double carry = 0.0;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        const double t = __builtin_fma(-q, cc.P40[k], s[k]) + carry;  // |t| < 2^53: exact
+        carry = floor(t * 0x1p-40);
+        const double d = __builtin_fma(-carry, 0x1p40, t);             // [0, 2^40)
+        const double hi = floor(d * 0x1p-32);
+        const double lo = __builtin_fma(-hi, 0x1p32, d);
+        ch[k] = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+    }
+    bool neg = carry < 0.0;
+    ch[KC] = neg ? 0xFFFFFFFFFFull : 0ull;  // sign extension of the chunk form
+    // 32-bit words of X (two's complement over 32 D bits)
+    uint32_t x[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const int k0 = (32 * j) / kChunkBits, o = 32 * j - kChunkBits * k0;
+        uint64_t v = ch[k0] >> o;
+        if (kChunkBits - o < 32) v |= ch[k0 + 1] << (kChunkBits - o);
+        x[j] = (uint32_t)v;
+    }
+    // |X|: complement and add one when negative
+    {
+        const uint32_t m = neg ? 0xFFFFFFFFu : 0u;
+        uint64_t c = neg ? 1u : 0u;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const uint64_t v = (uint64_t)(x[j] ^ m) + c;
+            x[j] = (uint32_t)v;
+            c = v >> 32;
+        }
+    }
+    // fallback: |X| > (P - 1) / 2  =>  |X| <- P - |X|, sign flipped
+    {
+        int64_t b = 0;  // borrow of half - |X|
+#pragma unroll
+        for (int j = 0; j < D; ++j) b = ((int64_t)cc.half[j] - (int64_t)x[j] + b) >> 32;
+        const bool over = b < 0;
+        int64_t br = 0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const int64_t v = (int64_t)cc.P[j] - (int64_t)x[j] + br;
+            x[j] = over ? (uint32_t)v : x[j];
+            br = v >> 32;
+        }
+        neg = neg != over;
+    }
+    int L = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) L = x[j] ? 32 * j + 32 - (int)__clz(x[j]) : L;
+    const int rb = max(L - 53, sc - 1074);
+    const int p = max(rb - 2, 0);
+    const int g = rb - p;  // bits to round off: 0, 1 or 2 (none when rb <= 0)
+    const int dw = p >> 5, sh = p & 31;
+    uint32_t a = 0, b = 0, c = 0, below = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const bool at = j == dw;
+        a = at ? x[j] : a;
+        b = at ? (j + 1 < D ? x[j + 1] : 0u) : b;
+        c = at ? (j + 2 < D ? x[j + 2] : 0u) : c;
+        below |= (j < dw) ? x[j] : 0u;
+    }
+    const uint32_t sticky = (below | (a & ((1u << sh) - 1u))) != 0u;
+    const uint32_t lo = __builtin_amdgcn_alignbit(b, a, sh) | sticky;
+    const uint32_t hi = __builtin_amdgcn_alignbit(c, b, sh);
+    const uint64_t w = ((uint64_t)hi << 32) | lo;
+    uint64_t t = w >> (g > 0 ? g : 0);
+    if (g > 0) {
+        const uint64_t rem = w & ((1ull << g) - 1ull), half = 1ull << (g - 1);
+        t += (rem > half || (rem == half && (t & 1ull))) ? 1ull : 0ull;
+    }
+    const double r = ldexp((double)t, (rb > 0 ? rb : 0) - sc);  // t <= 2^53: exact
+    return neg ? -r : r;
+}
+
 // Thread g of the output: row g / ceil(n / 4), four consecutive columns.
 // Residues are uint8 (INT8 moduli) or uint16 (float-channel moduli).
 template <int D, typename R = uint8_t>
@@ -113,50 +209,96 @@ __device__ __forceinline__ void reconstruct_body(const CrtConsts& cc, int64_t m,
     const int64_t i = g / per_row;
     const int64_t j0 = (g % per_row) * kPerThread;
     const int64_t plane = m_pad * n_pad;
-    int64_t acc[kPerThread][D];
-    double f[kPerThread];
+    // shifts first (clamped indices, unconditional loads), so that their
+    // latency hides behind the residue loop
+    const int32_t si = sa[i];
+    int32_t tj[kPerThread];
 #pragma unroll
-    for (int c = 0; c < kPerThread; ++c) {
-        f[c] = 0.0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) acc[c][d] = 0;
-    }
+    for (int c = 0; c < kPerThread; ++c) tj[c] = sb[(j0 + c < n) ? j0 + c : n - 1];
     const R* zp = Z + i * n_pad + j0;
-    for (int l = 0; l < cc.n; ++l) {
-        uint32_t zv[kPerThread];
-        if constexpr (sizeof(R) == 1) {
-            const uint32_t word = *reinterpret_cast<const uint32_t*>(zp + (int64_t)l * plane);
+    double out[kPerThread];
+    if constexpr (sizeof(R) == 1) {
+        // INT8 moduli: S = sum_l z_l N_l with N_l = inv_l M_l, congruent to
+        // the CRT sum modulo P, so no per-residue reduction is needed. S is
+        // summed in 40-bit chunks, each exactly in FP64: a product z_l
+        // N_l,k is below 2^48 and a chunk's sum over at most 32 moduli below
+        // 2^53. The residues of up to kBatch moduli are loaded before any is
+        // used, so that each wave keeps that many loads in flight (loads
+        // past the last modulus re-read the last plane and count as zeros).
+        constexpr int KC = (32 * D + kChunkBits - 1) / kChunkBits;
+        constexpr int kBatch = 16;
+        double sk[kPerThread][KC];
 #pragma unroll
-            for (int c = 0; c < kPerThread; ++c) zv[c] = (word >> (8 * c)) & 0xFFu;
-        } else {
+        for (int c = 0; c < kPerThread; ++c)
+#pragma unroll
+            for (int k = 0; k < KC; ++k) sk[c][k] = 0.0;
+        for (int l0 = 0; l0 < cc.n; l0 += kBatch) {
+            uint32_t word[kBatch];
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                const int l = (l0 + b < cc.n) ? l0 + b : cc.n - 1;
+                word[b] = __builtin_nontemporal_load(
+                    reinterpret_cast<const uint32_t*>(zp + (int64_t)l * plane));
+            }
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                const bool live = l0 + b < cc.n;
+                const int l = live ? l0 + b : cc.n - 1;
+                const uint32_t wb = live ? word[b] : 0u;
+#pragma unroll
+                for (int c = 0; c < kPerThread; ++c) {
+                    const double z = (double)((wb >> (8 * c)) & 0xFFu);
+#pragma unroll
+                    for (int k = 0; k < KC; ++k) sk[c][k] = __builtin_fma(z, cc.N40[l][k], sk[c][k]);
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kPerThread; ++c) {
+            out[c] = 0.0;
+            if (j0 + c >= n) continue;
+            if (si == kShiftNonFinite || tj[c] == kShiftNonFinite)
+                out[c] = __builtin_nan("");
+            else
+                out[c] = finish_chunks<D, KC>(cc, sk[c], si + tj[c]);
+        }
+    } else {
+        // float-channel moduli (up to 2^16): u_l = (z_l inv_l) mod m_l and
+        // S = sum_l u_l M_l in 32-bit digits, each term below 2^48
+        int64_t acc[kPerThread][D];
+        double f[kPerThread];
+#pragma unroll
+        for (int c = 0; c < kPerThread; ++c) f[c] = 0.0;
+#pragma unroll
+        for (int c = 0; c < kPerThread; ++c)
+#pragma unroll
+            for (int d = 0; d < D; ++d) acc[c][d] = 0;
+        for (int l = 0; l < cc.n; ++l) {
+            uint32_t zv[kPerThread];
             const uint2 w2 = *reinterpret_cast<const uint2*>(zp + (int64_t)l * plane);
             zv[0] = w2.x & 0xFFFFu;
             zv[1] = w2.x >> 16;
             zv[2] = w2.y & 0xFFFFu;
             zv[3] = w2.y >> 16;
+            const uint32_t ml = cc.m[l], mu = cc.mu[l], inv = cc.inv[l];
+            const double rcp = cc.rcp[l];
+#pragma unroll
+            for (int c = 0; c < kPerThread; ++c) {
+                const uint64_t u = barrett32(zv[c] * inv, ml, mu);
+                f[c] += (double)u * rcp;
+#pragma unroll
+                for (int d = 0; d < D; ++d) acc[c][d] += (int64_t)(u * cc.Ml[l][d]);
+            }
         }
-        const uint32_t ml = cc.m[l], mu = cc.mu[l], inv = cc.inv[l];
-        const double rcp = cc.rcp[l];
 #pragma unroll
         for (int c = 0; c < kPerThread; ++c) {
-            const uint64_t u = barrett32(zv[c] * inv, ml, mu);
-            f[c] += (double)u * rcp;
-#pragma unroll
-            for (int d = 0; d < D; ++d) acc[c][d] += (int64_t)(u * cc.Ml[l][d]);
+            out[c] = 0.0;
+            if (j0 + c >= n) continue;
+            if (si == kShiftNonFinite || tj[c] == kShiftNonFinite)
+                out[c] = __builtin_nan("");
+            else
+                out[c] = finish_one<D>(cc, acc[c], f[c], si + tj[c]);
         }
-    }
-    const int32_t si = sa[i];
-    double out[kPerThread];
-#pragma unroll
-    for (int c = 0; c < kPerThread; ++c) {
-        const int64_t j = j0 + c;
-        out[c] = 0.0;
-        if (j >= n) continue;
-        const int32_t tj = sb[j];
-        if (si == kShiftNonFinite || tj == kShiftNonFinite)
-            out[c] = __builtin_nan("");
-        else
-            out[c] = finish_one<D>(cc, acc[c], f[c], si + tj);
     }
     double* crow = C + i * ldc + j0;
     if (j0 + kPerThread <= n && ((reinterpret_cast<uintptr_t>(crow) & 15) == 0)) {

@@ -17,10 +17,14 @@ constexpr int kEncThreads = 256;
 constexpr int kEncVec = 16;   // consecutive k entries per thread (one 16-byte store per modulus)
 constexpr int kMaxShift = 80; // largest left shift of a significand: kBetaCap - 53 < 80
 
-// One entry, prepared once for all moduli. With kBig false the kept bits
-// are at most 63 and |A'| = mant 2^sh (or mant >> -sh) fits in 64 bits,
-// stored as two 32-bit words. With kBig true only mant is stored and a
-// positive shift is applied per modulus as a factor 2^sh mod m.
+// |A'| of one entry: the significand scaled by 2^(exponent + shift),
+// truncated toward zero (eq. "convert"), with its sign. Branch-free: every
+// lane of a wave takes the same instructions whatever its entry's class.
+// With kBig false the kept bits are at most 63 and |A'| = mant 2^sh (or
+// mant >> -sh) fits in 64 bits, stored as two 32-bit words. With kBig true
+// only mant >> max(-sh, 0) is stored and a positive sh is applied per
+// modulus as a factor 2^sh mod m. Non-finite entries and the marker shift
+// give zero.
 struct Entry {
     uint32_t lo, hi;
     int sh;    // > 0 only in the kBig form
@@ -30,49 +34,87 @@ struct Entry {
 template <bool kBig>
 __device__ __forceinline__ Entry make_entry(double x, int32_t shift) {
     Entry e;
-    uint64_t bits = (uint64_t)__double_as_longlong(x);
-    uint64_t a = bits & 0x7FFFFFFFFFFFFFFFull;
-    e.neg = (bits >> 63) != 0;
-    if (a >= 0x7FF0000000000000ull || shift == kShiftNonFinite) a = 0;  // non-finite: zero row
-    uint64_t mant;
-    int ex;
-    split_double(a, mant, ex);
-    int sh = ex + shift;
-    uint64_t v;
-    if (mant == 0) {
-        v = 0;
-        sh = 0;
-    } else if (sh <= 0) {
-        v = (sh <= -64) ? 0 : (mant >> (-sh));
-        sh = 0;
-    } else if (!kBig) {
-        v = mant << sh;  // sh <= 10: below 2^63
-        sh = 0;
-    } else {
-        v = mant;
-    }
+    const uint64_t bits = (uint64_t)__double_as_longlong(x);
+    const uint64_t a = bits & 0x7FFFFFFFFFFFFFFFull;
+    const bool keep = a < 0x7FF0000000000000ull && shift != kShiftNonFinite;
+    const uint32_t be = (uint32_t)(a >> 52);
+    const uint64_t mant = keep ? ((a & 0x000FFFFFFFFFFFFFull) | ((uint64_t)(be != 0) << 52)) : 0;
+    // exponent of the significand's unit: be - 1075, or -1074 for subnormals
+    const int sh = keep ? (int)(be > 1u ? be : 1u) - 1075 + shift : 0;
+    const int down = sh < 0 ? (-sh < 63 ? -sh : 63) : 0;  // mant < 2^53: >> 63 gives 0
+    uint64_t v = mant >> down;
+    if (!kBig) v = sh > 0 ? mant << sh : v;  // sh <= 10 here: below 2^63
     e.lo = (uint32_t)v;
     e.hi = (uint32_t)(v >> 32);
-    e.sh = sh;
+    e.sh = (kBig && sh > 0) ? sh : 0;
+    e.neg = (bits >> 63) != 0;
     return e;
 }
 
-// Balanced residue (int8) of the entry modulo m_l; p2 is the LDS table of
-// 2^s mod m_l (kBig only).
+// An entry in the form the INT8 residues use: the two's-complement bytes
+// of A' (of 2^64 - |A'| when A' < 0) and a mask that adds (-2^64) mod m per
+// modulus for those, so that sum_i byte_i 2^(8 i) + correction is congruent
+// to A' modulo every m.
+struct Entry8 {
+    uint32_t lo, hi;
+    uint32_t negm;  // all ones if A' < 0
+    int sh;
+};
+
 template <bool kBig>
-__device__ __forceinline__ int8_t entry_residue(const Entry& e, const ModConsts& mc, int l,
-                                                const uint8_t* p2) {
+__device__ __forceinline__ Entry8 make_entry8(double x, int32_t shift) {
+    const Entry e = make_entry<kBig>(x, shift);
+    const uint64_t v = ((uint64_t)e.hi << 32) | e.lo;
+    const bool neg = e.neg && v != 0;
+    const uint64_t w = neg ? (uint64_t)0 - v : v;
+    Entry8 r;
+    r.lo = (uint32_t)w;
+    r.hi = (uint32_t)(w >> 32);
+    r.negm = neg ? 0xFFFFFFFFu : 0u;
+    r.sh = e.sh;
+    return r;
+}
+
+// Balanced residue t - m floor(t / m + 1/2), in [-floor(m/2), ceil(m/2) - 1],
+// of t < 2^19. With rcp_up = 1/m rounded up, fma(t, rcp_up, 1/2) is never
+// below t/m + 1/2 and exceeds it by less than 1/(8m) + 2^-24, while the
+// distance from t/m + 1/2 up to the next integer is at least 1/(2m) (when
+// m divides 2t + m, the value is itself an integer and is kept): the
+// truncated sum is floor(t/m + 1/2) exactly.
+__device__ __forceinline__ int32_t balanced19(uint32_t t, uint32_t m, float rcp_up) {
+    const uint32_t q = (uint32_t)__builtin_fmaf((float)t, rcp_up, 0.5f);
+    return (int32_t)t + __mul24((int32_t)q, -(int32_t)m);
+}
+
+// Balanced residue of the entry modulo m_l, as an int32 in [-128, 127]; p2
+// is the LDS table of 2^s mod m_l (kBig only). The two byte dot products
+// sum at most 8 * 255 * 255 + 255 < 2^19.
+template <bool kBig>
+__device__ __forceinline__ int32_t entry_residue(const Entry8& e, const ModConsts& mc, int l,
+                                                 const uint8_t* p2) {
     const uint32_t m = mc.m[l];
-    const float rcp = mc.rcp[l];
-    // sum of the eight bytes of |A'| times 2^(8 i) mod m: below 2^20, so the
-    // FP32-reciprocal reduction is exact
-    uint32_t t = __builtin_amdgcn_udot4(e.lo, mc.w8[l][0], 0u, false);
+    uint32_t t = __builtin_amdgcn_udot4(e.lo, mc.w8[l][0], e.negm & mc.c64n[l], false);
     t = __builtin_amdgcn_udot4(e.hi, mc.w8[l][1], t, false);
-    uint32_t r = mod24(t, m, rcp);
-    if (kBig && e.sh > 0) r = mod24(r * p2[e.sh], m, rcp);
-    if (e.neg) r = r ? m - r : 0;
-    const int32_t v = (r >= (m + 1) / 2) ? (int32_t)r - (int32_t)m : (int32_t)r;
-    return (int8_t)v;
+    if (kBig && e.sh > 0) t = mod24(t, m, mc.rcp[l]) * p2[e.sh];  // below 2^16
+    return balanced19(t, m, mc.rcp_up[l]);
+}
+
+// Low bytes of four values, a in byte 0.
+__device__ __forceinline__ uint32_t pack4(int32_t a, int32_t b, int32_t c, int32_t d) {
+    const uint32_t ab = __builtin_amdgcn_perm((uint32_t)b, (uint32_t)a, 0x0c0c0400u);
+    const uint32_t cd = __builtin_amdgcn_perm((uint32_t)d, (uint32_t)c, 0x0c0c0400u);
+    return __builtin_amdgcn_perm(cd, ab, 0x05040100u);
+}
+
+// Sixteen residues of one modulus as one 16-byte word, entry q in byte q.
+template <bool kBig>
+__device__ __forceinline__ uint4 residues16(const Entry8* ent, const ModConsts& mc, int l,
+                                            const uint8_t* p2) {
+    int32_t r[kEncVec];
+#pragma unroll
+    for (int q = 0; q < kEncVec; ++q) r[q] = entry_residue<kBig>(ent[q], mc, l, p2);
+    return make_uint4(pack4(r[0], r[1], r[2], r[3]), pack4(r[4], r[5], r[6], r[7]),
+                      pack4(r[8], r[9], r[10], r[11]), pack4(r[12], r[13], r[14], r[15]));
 }
 
 // Shift of an entry whose row (or column) shift is s and whose inner index
@@ -85,11 +127,6 @@ __device__ __forceinline__ int32_t entry_shift(int32_t s, const int32_t* fold, i
         const int32_t f = fold[h];
         return (s == kShiftNonFinite || f == kShiftNonFinite) ? kShiftNonFinite : s - f;
     }
-}
-
-__device__ __forceinline__ uint32_t pack4(const int8_t* v) {
-    return (uint32_t)(uint8_t)v[0] | ((uint32_t)(uint8_t)v[1] << 8) |
-           ((uint32_t)(uint8_t)v[2] << 16) | ((uint32_t)(uint8_t)v[3] << 24);
 }
 
 // Table of 2^s mod m_l for s < kMaxShift in LDS (kBig only).
@@ -130,7 +167,7 @@ __device__ __forceinline__ void encode_a_body(const ModConsts& mc, int64_t m, in
             *reinterpret_cast<uint4*>(out + (int64_t)l * plane_stride) = make_uint4(0, 0, 0, 0);
         return;
     }
-    Entry ent[kEncVec];
+    Entry8 ent[kEncVec];
     const int32_t s = shift_a[i];
     const double* row = A + i * lda;
     if (h + kEncVec <= k && ((reinterpret_cast<uintptr_t>(row + h) & 15) == 0)) {
@@ -138,28 +175,20 @@ __device__ __forceinline__ void encode_a_body(const ModConsts& mc, int64_t m, in
 #pragma unroll
         for (int q = 0; q < kEncVec / 2; ++q) {
             double2 v = p2v[q];
-            ent[2 * q] = make_entry<kBig>(v.x, entry_shift<kFold>(s, fold, h + 2 * q));
-            ent[2 * q + 1] = make_entry<kBig>(v.y, entry_shift<kFold>(s, fold, h + 2 * q + 1));
+            ent[2 * q] = make_entry8<kBig>(v.x, entry_shift<kFold>(s, fold, h + 2 * q));
+            ent[2 * q + 1] = make_entry8<kBig>(v.y, entry_shift<kFold>(s, fold, h + 2 * q + 1));
         }
     } else {
 #pragma unroll
         for (int q = 0; q < kEncVec; ++q) {
             const bool in = h + q < k;
             double v = in ? row[h + q] : 0.0;
-            ent[q] = make_entry<kBig>(v, in ? entry_shift<kFold>(s, fold, h + q) : 0);
+            ent[q] = make_entry8<kBig>(v, in ? entry_shift<kFold>(s, fold, h + q) : 0);
         }
     }
-    for (int l = 0; l < mc.n; ++l) {
-        int8_t r[kEncVec];
-#pragma unroll
-        for (int q = 0; q < kEncVec; ++q) r[q] = entry_residue<kBig>(ent[q], mc, l, p2 + l * kMaxShift);
-        uint4 w;
-        w.x = pack4(r);
-        w.y = pack4(r + 4);
-        w.z = pack4(r + 8);
-        w.w = pack4(r + 12);
-        *reinterpret_cast<uint4*>(out + (int64_t)l * plane_stride) = w;
-    }
+    for (int l = 0; l < mc.n; ++l)
+        *reinterpret_cast<uint4*>(out + (int64_t)l * plane_stride) =
+            residues16<kBig>(ent, mc, l, p2 + l * kMaxShift);
 }
 
 // grid: ceil(m_pad * k_pad / 16 / 256).
@@ -206,23 +235,16 @@ __device__ __forceinline__ void encode_b_body(const ModConsts& mc, int64_t k, in
     const int hq = threadIdx.x >> 6;  // 0..3
     const int64_t j = j0 + tj;
     const int32_t s = (j < n) ? shift_b[j] : 0;
-    Entry ent[kEncVec];
+    Entry8 ent[kEncVec];
 #pragma unroll
     for (int q = 0; q < kEncVec; ++q) {
         const int64_t h = h0 + hq * kEncVec + q;
         const bool in = j < n && h < k;
         double v = in ? B[h * ldb + j] : 0.0;
-        ent[q] = make_entry<kBig>(v, in ? entry_shift<kFold>(s, fold, h) : 0);
+        ent[q] = make_entry8<kBig>(v, in ? entry_shift<kFold>(s, fold, h) : 0);
     }
     for (int l = 0; l < mc.n; ++l) {
-        int8_t r[kEncVec];
-#pragma unroll
-        for (int q = 0; q < kEncVec; ++q) r[q] = entry_residue<kBig>(ent[q], mc, l, p2 + l * kMaxShift);
-        uint4 w;
-        w.x = pack4(r);
-        w.y = pack4(r + 4);
-        w.z = pack4(r + 8);
-        w.w = pack4(r + 12);
+        const uint4 w = residues16<kBig>(ent, mc, l, p2 + l * kMaxShift);
         if (l > 0) __syncthreads();  // previous modulus fully copied out
         *reinterpret_cast<uint4*>(tile + tj * kLdsRow + hq * kEncVec) = w;
         __syncthreads();

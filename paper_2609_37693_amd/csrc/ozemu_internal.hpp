@@ -10,6 +10,8 @@ namespace ozemu {
 
 constexpr int kMaxModuli = 32;  // moduli per plan
 constexpr int kMaxDigits = 10;  // 32-bit digits of CRT sums: N * P < 2^(8*32 + 5)
+constexpr int kChunkBits = 40;  // FP64 chunks of CRT sums with INT8 moduli
+constexpr int kMaxChunks = 7;   // 40-bit chunks of P + 2 bits for at most 32 moduli of <= 2^8
 constexpr int kBetaCap = 127;   // largest kept-bit count of any mode
 
 // Residue GEMM tiling. Planes are padded to whole tiles, so the GEMM kernel
@@ -49,6 +51,8 @@ struct ModConsts {
     float rcp[kMaxModuli];     // 1 / m rounded to FP32
     uint16_t w12[kMaxModuli][6];  // 2^(12 i) mod m, i = 0..5
     uint32_t w8[kMaxModuli][2];   // bytes 2^(8 i) mod m, i = 0..3 and 4..7 (m <= 256)
+    float rcp_up[kMaxModuli];     // 1 / m rounded up to FP32
+    uint32_t c64n[kMaxModuli];    // (-2^64) mod m
 };
 
 // t mod m for t < 2^24 and 2 <= m <= 256: t is exact in FP32 and t * rcp
@@ -111,7 +115,14 @@ struct CrtConsts {
     uint32_t Ml[kMaxModuli][kMaxDigits];
     uint32_t P[kMaxDigits];
     uint32_t half[kMaxDigits];  // floor((P - 1) / 2)
+    // INT8 moduli: N_l = inv_l M_l (below P) and P in 40-bit chunks held
+    // exactly in FP64, and 2^(40 k) / P rounded to FP64
+    int kc;
+    double N40[kMaxModuli][kMaxChunks];
+    double P40[kMaxChunks];
+    double R40[kMaxChunks];
 };
+static_assert(sizeof(CrtConsts) + 128 <= 4096, "CRT constants travel as a kernel argument");
 
 // x mod m for x < 2^32, m in [2, 2^16]; mu = floor(2^32 / m).
 __host__ __device__ __forceinline__ uint32_t barrett32(uint32_t x, uint32_t m, uint32_t mu) {

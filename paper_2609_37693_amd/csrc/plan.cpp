@@ -201,6 +201,16 @@ std::string build_plan(Plan& p, int format, const std::vector<int>& moduli_in, i
     return fill_moduli(p, ms);
 }
 
+// Bits [40 c, 40 c + 40) of a big integer.
+static uint64_t chunk40(const BigU& x, int c) {
+    uint64_t v = 0;
+    for (int b = 0; b < kChunkBits; ++b) {
+        const int bit = kChunkBits * c + b;
+        if (bit / 32 < BigU::cap && ((x.d[bit / 32] >> (bit % 32)) & 1u)) v |= 1ull << b;
+    }
+    return v;
+}
+
 // P, caps, Barrett, digit-weight and CRT constants of a sorted modulus set.
 std::string fill_moduli(Plan& p, const std::vector<int>& ms) {
     const int n = (int)ms.size();
@@ -232,6 +242,13 @@ std::string fill_moduli(Plan& p, const std::vector<int>& ms) {
             for (int b = 0; b < 12 * i; ++b) w = (w * 2) % m;
             p.mod.w12[l][i] = (uint16_t)w;
         }
+        {
+            float r = 1.0f / (float)m;
+            if ((double)r * (double)m < 1.0) r = std::nextafter(r, 1.0f);  // exact test
+            p.mod.rcp_up[l] = r;
+            const uint64_t c = (uint64_t)((((unsigned __int128)1) << 64) % m);
+            p.mod.c64n[l] = (uint32_t)((m - c) % m);
+        }
         p.mod.w8[l][0] = p.mod.w8[l][1] = 0;
         if (m <= 256)
             for (int i = 0; i < 8; ++i) {
@@ -252,6 +269,20 @@ std::string fill_moduli(Plan& p, const std::vector<int>& ms) {
         if (m == 1 || inv == 0) return "internal: no inverse";
         p.crt.inv[l] = inv;
         for (int i = 0; i < kMaxDigits; ++i) p.crt.Ml[l][i] = Ml.d[i];
+        // N_l = inv_l M_l < m_l M_l = P, in 40-bit chunks
+        BigU Nl = Ml;
+        Nl.mul_small(inv);
+        for (int c = 0; c < kMaxChunks; ++c) p.crt.N40[l][c] = (double)chunk40(Nl, c);
+    }
+    p.crt.kc = (p.p_bits + 2 + kChunkBits - 1) / kChunkBits;
+    if (p.mod.m[0] <= 256 && p.crt.kc > kMaxChunks) return "modulus product too large";
+    {
+        double Pd = 0;  // P to within a few ulps
+        for (int i = BigU::cap - 1; i >= 0; --i) Pd = Pd * 4294967296.0 + p.P.d[i];
+        for (int c = 0; c < kMaxChunks; ++c) {
+            p.crt.P40[c] = (double)chunk40(p.P, c);
+            p.crt.R40[c] = std::ldexp(1.0 / Pd, kChunkBits * c);
+        }
     }
     BigU half = p.P;
     BigU one = BigU::from_u64(1);
