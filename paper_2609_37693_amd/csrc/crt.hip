@@ -103,35 +103,43 @@ __device__ __forceinline__ double finish_one(const CrtConsts& cc, int64_t* acc, 
 
 // Finishes one entry from its CRT sum S = sum_l z_l N_l held as KC
 // FP64 chunks s_k (S = sum_k s_k 2^(40 k), each s_k an integer below
-// 2^53) with INT8 moduli. Branch-free: q = rint(sum_k s_k 2^(40 k) / P)
-// (within 2^-30 of S / P); X = S - q P chunk by chunk, exact, then carried
-// into 40-bit chunks in [0, 2^40) whose last carry (-1 or 0) is the sign;
-// the chunks give the 32-bit words of X, two's complement, then of |X|
-// (fallback as in finish_one). The rounding position is
-// rb = max(L - 53, sc - 1074) for the bit length L of |X|: the 64 bits of
-// |X| from p = max(rb - 2, 0) up, the bits below p folded into the lowest
-// (they are only a sticky bit), are rounded at rb to nearest even in
-// integer arithmetic and scaled exactly.
+// 2^53) with INT8 moduli. f = sum_k s_k 2^(40 k) / P is within 2^-34 of
+// S / P and q = rint(f). When e = f - q is at least 2^-30 from 0 and from
+// +-1/2 (nearly always), q is the nearest integer to S / P and X = S - q P
+// has the sign of e: sg X is formed chunk by chunk (exact) and carried
+// into 40-bit chunks in [0, 2^40), which give the 32-bit words of |X|.
+// Otherwise X itself is formed, its last carry (-1 or 0) is the sign, the
+// words are complemented when negative, and the exact fallback of
+// finish_one applies. The rounding position is rb = max(L - 53, sc - 1074)
+// for the bit length L of |X|: the 64 bits of |X| from p = max(rb - 2, 0)
+// up, the bits below p folded into the lowest (they are only a sticky
+// bit), are rounded at rb to nearest even in integer arithmetic and scaled
+// exactly.
 template <int D, int KC>
 __device__ __forceinline__ double finish_chunks(const CrtConsts& cc, const double* s, int sc) {
     double f = 0.0;
 #pragma unroll
     for (int k = 0; k < KC; ++k) f = __builtin_fma(s[k], cc.R40[k], f);
     const double q = rint(f);
+    const double e = f - q;
+    const bool fast = fabs(e) >= 0x1p-30 && fabs(e) <= 0.5 - 0x1p-30;
+    const double sg = (fast && e < 0.0) ? -1.0 : 1.0;
+    const double qs = q * sg;
     uint64_t ch[KC + 1];
     double carry = 0.0;
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
-        const double t = __builtin_fma(-q, cc.P40[k], s[k]) + carry;  // |t| < 2^53: exact
+        // |t| < 2^53: exact
+        const double t = __builtin_fma(-qs, cc.P40[k], s[k] * sg) + carry;
         carry = floor(t * 0x1p-40);
-        const double d = __builtin_fma(-carry, 0x1p40, t);             // [0, 2^40)
+        const double d = __builtin_fma(-carry, 0x1p40, t);  // [0, 2^40)
         const double hi = floor(d * 0x1p-32);
         const double lo = __builtin_fma(-hi, 0x1p32, d);
         ch[k] = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
     }
-    bool neg = carry < 0.0;
+    bool neg = carry < 0.0;  // false on the fast path
     ch[KC] = neg ? 0xFFFFFFFFFFull : 0ull;  // sign extension of the chunk form
-    // 32-bit words of X (two's complement over 32 D bits)
+    // 32-bit words of sg X (two's complement over 32 D bits)
     uint32_t x[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -140,8 +148,10 @@ __device__ __forceinline__ double finish_chunks(const CrtConsts& cc, const doubl
         if (kChunkBits - o < 32) v |= ch[k0 + 1] << (kChunkBits - o);
         x[j] = (uint32_t)v;
     }
-    // |X|: complement and add one when negative
-    {
+    if (fast) {
+        neg = sg < 0.0;
+    } else {
+        // |X|: complement and add one when negative
         const uint32_t m = neg ? 0xFFFFFFFFu : 0u;
         uint64_t c = neg ? 1u : 0u;
 #pragma unroll
@@ -150,9 +160,7 @@ __device__ __forceinline__ double finish_chunks(const CrtConsts& cc, const doubl
             x[j] = (uint32_t)v;
             c = v >> 32;
         }
-    }
-    // fallback: |X| > (P - 1) / 2  =>  |X| <- P - |X|, sign flipped
-    {
+        // fallback: |X| > (P - 1) / 2  =>  |X| <- P - |X|, sign flipped
         int64_t b = 0;  // borrow of half - |X|
 #pragma unroll
         for (int j = 0; j < D; ++j) b = ((int64_t)cc.half[j] - (int64_t)x[j] + b) >> 32;

@@ -264,3 +264,57 @@ def test_tall_products_match_oracle(shape, mode, nmod):
     ref = scheme.emulate(A, B, plan.moduli(), mode, blas=True, keep=False)["C"]
     assert np.array_equal(host(C1), ref)
     assert np.array_equal(host(C2), ref)
+
+
+_ODD16 = [251, 241, 239, 233, 229, 227, 223, 211, 199, 197, 193, 191, 181, 179, 173, 167]
+
+
+@pytest.mark.parametrize("moduli", [None, _ODD16])
+def test_reconstruct_crt_edge_values(moduli):
+    """Reconstruct alone, on the residues of chosen X: 0, +-1, the ends of
+    the balanced range +-(P-1)/2 (where the estimate of the nearest multiple
+    of P may be off by one), values next to P 2^-30 and P/2 - P 2^-30 (where
+    the sign is or is not read from the estimate), rounding ties at 2^53,
+    2^54, 2^64 and 2^100, and random values; row shifts that give normal,
+    subnormal, zero and infinite results; a column with the non-finite
+    marker gives NaN. Bitwise equal to the oracle's one rounding of
+    X 2^-(s_i + t_j). The default set holds 256 (P even), the other only
+    odd moduli."""
+    import torch
+    from oracle import exact
+    plan = oz.Plan(num_moduli=16, scaling="W") if moduli is None else \
+        oz.Plan(scaling="W", moduli=moduli)
+    ms = plan.moduli()
+    P = 1
+    for mm in ms:
+        P *= mm
+    half = (P - 1) // 2
+    e30, e31 = P >> 30, P >> 31
+    xs = [0, 1, 2, 3, half, half - 1, half - 2 ** 20, e30, e30 - 1, e30 + 1, e31,
+          half - e30, half - e30 - 1, half - e30 + 1, half - e31,
+          2 ** 53 + 1, 2 ** 53 + 3, 2 ** 54 + 2, 2 ** 54 + 6, 2 ** 64 + 2 ** 11,
+          2 ** 64 + 3 * 2 ** 11, 2 ** 100 + 2 ** 47, 2 ** 100 + 2 ** 47 + 1]
+    xs = xs + [-x for x in xs if x]
+    rng = np.random.default_rng(11)
+    xs += [int(v) for v in rng.integers(-2 ** 62, 2 ** 62, 8)]
+    xs += [int.from_bytes(rng.bytes(16), "little") % P - half for _ in range(12)]
+    row_shifts = [0, 40, -40, 1000, 1060, 1100, 1150, 1200, 1300, -900, -1100]
+    m, n, k = len(row_shifts), len(xs) + 1, 64
+    mp, np_, _ = plan.plane_dims(m, n, k)
+    Z = np.zeros((len(ms), mp, np_), dtype=np.uint8)
+    X = np.zeros((m, n), dtype=object)
+    for j, x in enumerate(xs):
+        X[:, j] = x
+    for l, mm in enumerate(ms):
+        Z[l, :m, :n] = np.vectorize(lambda v: int(v) % mm, otypes=[np.int64])(X)
+    sa = np.array(row_shifts, dtype=np.int32)
+    sb = np.zeros(n, dtype=np.int32)
+    sb[n - 1] = -(2 ** 31)  # the non-finite marker
+    C = host(oz.reconstruct(dev(Z), dev(sa), dev(sb), m, n, k, plan))
+    torch.cuda.synchronize()
+    for i in range(m):
+        for j in range(n - 1):
+            want = exact.round_ratio_to_double(int(X[i, j]), int(sa[i]))
+            got = C[i, j]
+            assert got == want and np.signbit(got) == np.signbit(want), (i, j, xs[j], row_shifts[i])
+    assert np.isnan(C[:, n - 1]).all()
