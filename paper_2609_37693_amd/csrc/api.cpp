@@ -793,9 +793,9 @@ ozemu_status ozemu_group_create(ozemu_group* out, int count, const ozemu_plan* p
         const int64_t T = (P.m_pad / kTileM) * (P.n_pad / kTileN);
         for (int x = 0; x < kXcds; ++x) {
             prefix[(size_t)(kGTiles + x) * (count + 1) + q] = (int32_t)tot[kGTiles + x];
-            int64_t lo, hi;
-            xcd_share(T, x, q, lo, hi);
-            if (work) tot[kGTiles + x] += (int64_t)uniq[P.plan]->n * (hi - lo);
+            int first, cnt;
+            xcd_moduli(uniq[P.plan]->n, x, q, first, cnt);
+            if (work) tot[kGTiles + x] += (int64_t)cnt * T;
         }
     }
     for (int kind = 0; kind < kGKinds; ++kind) {

@@ -111,7 +111,8 @@ __device__ __forceinline__ void barrier_no_fence() {
 // One 256 x 256 output tile (tm, tn) over K = k_pad (a positive multiple of
 // 64): gA and gB point at the first block of the tile's row strip in the A
 // and B planes of one modulus (plane_offset order), gZ at the tile's first
-// residue (row stride n_pad). Modulus m with Barrett constant mu (kMod);
+// residue (row stride n_pad). Modulus m (kMod; mu is the Barrett constant
+// of the float-channel epilogue);
 // row/column maxima into gmax_a/gmax_b (kMax). `lds` holds
 // S * kDStage bytes (a ring of S K steps, loads issued S - 1 steps ahead);
 // the caller synchronizes before reusing it.
@@ -410,6 +411,22 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
         }
     } else if constexpr (E == Epi::kMod) {
         uint8_t* sO = reinterpret_cast<uint8_t*>(lds);
+        // w mod m in [0, m) for any INT32 w: t = (w >> 16) (2^16 mod m) +
+        // (w & 0xFFFF) is congruent to w with |t| < 2^24, exact in FP32;
+        // floor(t * rcp) is floor(t / m) or one off (|t * rcp - t / m| <
+        // 2 / m <= 1), so t - q m lies in [-m, 2m) and two unsigned-min
+        // steps bring it into [0, m). Twelve full-rate instructions.
+        uint32_t c16 = __builtin_amdgcn_readfirstlane(65536u % m);
+        asm volatile("" : "+s"(c16));  // opaque range: keeps the 24-bit multiply-add
+        const float rcp = __builtin_bit_cast(
+            float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(uint32_t, 1.0f / (float)m)));
+        auto mod_m = [&](int32_t w) -> uint32_t {
+            const int32_t t = __mul24(w >> 16, (int32_t)c16) + (w & 0xFFFF);
+            const int32_t q = (int32_t)floorf((float)t * rcp);
+            uint32_t r = (uint32_t)(t + __mul24(q, -(int32_t)m));
+            r = min(r, r + m);
+            return min(r, r - m);
+        };
 #pragma unroll
         for (int a = 0; a < kFM; ++a) {
 #pragma unroll
@@ -418,13 +435,7 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
                 for (int g = 0; g < 4; ++g) {
                     uint32_t packed = 0;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int32_t w = acc[a][b][4 * g + q];
-                        const uint32_t aw = (uint32_t)(w < 0 ? -w : w);
-                        uint32_t r = barrett32(aw, m, mu);
-                        if (w < 0 && r != 0) r = m - r;
-                        packed |= r << (8 * q);
-                    }
+                    for (int q = 0; q < 4; ++q) packed |= mod_m(acc[a][b][4 * g + q]) << (8 * q);
                     const int i = wi * kWaveM + a * 32 + li;
                     const int j = wj * kWaveN + b * 32 + 8 * g + lj;
                     *reinterpret_cast<uint32_t*>(sO + i * kOutRow + j) = packed;
@@ -526,8 +537,10 @@ __global__ __launch_bounds__(kThreads) void fp_gemm_kernel(FpGemmArgs g) {
 // Grouped residue GEMM, persistent: workgroup b starts on the list of its
 // XCD (b % 8, the hardware's round-robin placement) and takes work items
 // (problem, modulus, tile) from that list's counter; when it is exhausted
-// it helps the other XCDs' lists in turn. Every wave of a workgroup sees the
-// same item, so all waves leave the loops together.
+// it helps the other XCDs' lists in turn. An XCD's list holds whole moduli
+// of each problem (every tile, in band order), so its workgroups share the
+// operand strips of one modulus in their L2. Every wave of a workgroup sees
+// the same item, so all waves leave the loops together.
 __global__ __launch_bounds__(kThreads) void group_gemm_kernel(GroupArgs g) {
     __shared__ __align__(1024) int8_t lds[kDStages * kDStage];
     __shared__ int32_t next;
@@ -545,13 +558,14 @@ __global__ __launch_bounds__(kThreads) void group_gemm_kernel(GroupArgs g) {
             const int q = group_find(pre, g.count, w);
             const GProblem& P = g.probs[g.order[q]];
             const int tiles_m = (int)(P.m_pad / kBM), tiles_n = (int)(P.n_pad / kBN);
-            int64_t lo, hi;
-            xcd_share((int64_t)tiles_m * tiles_n, x, q, lo, hi);
-            const int64_t local = w - pre[q];
-            const int l = (int)(local / (hi - lo));
-            int tm, tn;
-            band_tile(lo + local % (hi - lo), tiles_m, tiles_n, tm, tn);
+            const int64_t T = (int64_t)tiles_m * tiles_n;
             const ModConsts& mc = g.mods[P.plan];
+            int first, cnt;
+            xcd_moduli(mc.n, x, q, first, cnt);
+            const int64_t local = w - pre[q];  // < cnt * T
+            const int l = first + kXcds * (int)(local / T);
+            int tm, tn;
+            band_tile(local % T, tiles_m, tiles_n, tm, tn);
             const int8_t* gA = reinterpret_cast<const int8_t*>(g.ws + P.off_pa) +
                                (int64_t)l * P.m_pad * P.k_pad + (int64_t)tm * kBM * P.k_pad;
             const int8_t* gB = reinterpret_cast<const int8_t*>(g.ws + P.off_pb) +

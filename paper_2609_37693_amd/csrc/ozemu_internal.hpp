@@ -266,13 +266,14 @@ enum GKind : int {
     kGKinds = kGTiles + kXcds
 };
 
-// Tiles [lo, hi) of T that XCD x takes for the q-th problem in GEMM order
-// (the eighths rotate with q so that remainders spread over the XCDs).
-__host__ __device__ __forceinline__ void xcd_share(int64_t T, int x, int q, int64_t& lo,
-                                                   int64_t& hi) {
-    const int r = (x + q) & (kXcds - 1);
-    lo = (int64_t)r * T / kXcds;
-    hi = (int64_t)(r + 1) * T / kXcds;
+// Moduli that XCD x takes, with every tile of each, for the q-th problem
+// in GEMM order: l = first, first + 8, ... (count of them). The XCD's
+// workgroups then run the tiles of one modulus together, so that the
+// operand strips they share stay in that XCD's L2; the residue rotates with
+// q so that remainders spread over the XCDs.
+__host__ __device__ __forceinline__ void xcd_moduli(int N, int x, int q, int& first, int& count) {
+    first = (x + q) & (kXcds - 1);
+    count = first < N ? (N - 1 - first) / kXcds + 1 : 0;
 }
 
 struct GProblem {
