@@ -411,21 +411,33 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
         }
     } else if constexpr (E == Epi::kMod) {
         uint8_t* sO = reinterpret_cast<uint8_t*>(lds);
-        // w mod m in [0, m) for any INT32 w: t = (w >> 16) (2^16 mod m) +
-        // (w & 0xFFFF) is congruent to w with |t| < 2^24, exact in FP32;
-        // floor(t * rcp) is floor(t / m) or one off (|t * rcp - t / m| <
-        // 2 / m <= 1), so t - q m lies in [-m, 2m) and two unsigned-min
-        // steps bring it into [0, m). Twelve full-rate instructions.
+        // w mod m in [0, m) for any INT32 w. t = (w >> 16) (2^16 mod m) +
+        // (w & 0xFFFF), formed as w + (w >> 16) (c16 - 2^16) in one 24-bit
+        // multiply-add, is congruent to w with |t| < 2^15 m + 2^16.
+        // fma(t, rcp, 1.5 2^23) holds 1.5 2^23 + q, q the nearest integer
+        // to t rcp (within 1/2 + 1/m of t / m), in its low mantissa bits, so
+        // t - m x24 (x24 = low 24 bits = 2^22 + q) is t - q m - 2^22 m: its
+        // low 16 bits are r = t - q m in [-m/2 - 1, m/2 + 1] (2^22 m is a
+        // multiple of 2^16). Pairs of r then take two unsigned-min steps in
+        // packed 16-bit arithmetic into [0, m). Exhaustively checked on the
+        // CPU for every m <= 256 and every t.
         uint32_t c16 = __builtin_amdgcn_readfirstlane(65536u % m);
         asm volatile("" : "+s"(c16));  // opaque range: keeps the 24-bit multiply-add
+        const int32_t kadj = (int32_t)c16 - 65536;
         const float rcp = __builtin_bit_cast(
             float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(uint32_t, 1.0f / (float)m)));
-        auto mod_m = [&](int32_t w) -> uint32_t {
-            const int32_t t = __mul24(w >> 16, (int32_t)c16) + (w & 0xFFFF);
-            const int32_t q = (int32_t)floorf((float)t * rcp);
-            uint32_t r = (uint32_t)(t + __mul24(q, -(int32_t)m));
-            r = min(r, r + m);
-            return min(r, r - m);
+        const int32_t negm = -(int32_t)m;
+        using u16x2 = unsigned short __attribute__((ext_vector_type(2)));
+        const u16x2 m2 = {(unsigned short)m, (unsigned short)m};
+        auto r16 = [&](int32_t w) -> uint32_t {
+            const int32_t t = __mul24(w >> 16, kadj) + w;
+            const float x = __builtin_fmaf((float)t, rcp, 12582912.0f);
+            return (uint32_t)(t + __mul24(__builtin_bit_cast(int32_t, x), negm));
+        };
+        auto fix2 = [&](uint32_t lo, uint32_t hi) -> u16x2 {
+            u16x2 v = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(hi, lo, 0x05040100u));
+            v = __builtin_elementwise_min(v, v + m2);
+            return __builtin_elementwise_min(v, v - m2);
         };
 #pragma unroll
         for (int a = 0; a < kFM; ++a) {
@@ -433,9 +445,11 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
             for (int b = 0; b < kFN; ++b) {
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
-                    uint32_t packed = 0;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) packed |= mod_m(acc[a][b][4 * g + q]) << (8 * q);
+                    const int32_t* w = reinterpret_cast<const int32_t*>(&acc[a][b]) + 4 * g;
+                    const u16x2 v01 = fix2(r16(w[0]), r16(w[1]));
+                    const u16x2 v23 = fix2(r16(w[2]), r16(w[3]));
+                    const uint32_t packed = __builtin_amdgcn_perm(
+                        __builtin_bit_cast(uint32_t, v23), __builtin_bit_cast(uint32_t, v01), 0x06040200u);
                     const int i = wi * kWaveM + a * 32 + li;
                     const int j = wj * kWaveN + b * 32 + 8 * g + lj;
                     *reinterpret_cast<uint32_t*>(sO + i * kOutRow + j) = packed;
