@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=32,
                     help="rows of C in the CPU oracle's bounded sample")
     ap.add_argument("--no-native", action="store_true")
-    ap.add_argument("--format", default="E4M3", choices=["E4M3", "E2M1"],
+    ap.add_argument("--format", default="E4M3", choices=["E4M3", "E2M3", "E2M1"],
                     help="fp workload: float alphabet of the limb channels")
     ap.add_argument("--gemms-list", default="0",
                     help="fp workload: comma-separated GEMM counts (0: least count for the "
@@ -434,7 +434,7 @@ def fp_main(args):
         "value": head["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": head["ms"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "fp8" if args.format == "E4M3" else "fp4", "data": "synthetic",
+        "dtype": {"E4M3": "fp8", "E2M3": "fp6", "E2M1": "fp4"}[args.format], "data": "synthetic",
         "config": {"workload": "emulated DGEMM m=n=k=%d, phi = 1, %s channels, FP32 "
                                "accumulation, slabs of 16384" % (n, args.format),
                    "format": args.format, "gemms": head["gemms"]},

@@ -51,7 +51,7 @@ typedef enum {
 typedef enum {
     OZEMU_INT8 = 0,  /* one INT8 GEMM per modulus, moduli <= 256 (Sec. IV-C)      */
     OZEMU_E4M3 = 1,  /* FP8 limb channels, FP32 accumulation (Sec. III-B, IV-A)  */
-    OZEMU_E2M3 = 2,  /* FP6: not built (OZEMU_ERR_UNSUPPORTED)                   */
+    OZEMU_E2M3 = 2,  /* FP6 limb channels, FP32 accumulation (Sec. III-B, IV-A)  */
     OZEMU_E2M1 = 3   /* FP4 limb channels, FP32 accumulation (Sec. III-B, IV-B)  */
 } ozemu_format;
 
@@ -87,8 +87,11 @@ ozemu_status ozemu_plan_create(ozemu_plan* out, int format, int num_moduli, int 
 ozemu_status ozemu_plan_create_moduli(ozemu_plan* out, int format, int count,
                                       const int32_t* moduli, int scaling);
 
-/* Plan over limb channels of a float alphabet (format OZEMU_E4M3 or
- * OZEMU_E2M1), for ozemu_dgemm (the other entry points take INT8 plans).
+/* Plan over limb channels of a float alphabet (format OZEMU_E4M3,
+ * OZEMU_E2M3 or OZEMU_E2M1), for ozemu_dgemm (the other entry points take
+ * INT8 plans). E2M3 scales its values by 2^3 and, within radius 32, holds
+ * the same 49 integers as E4M3 (Example "equivalence"), so both pick the
+ * same channels at k_slab = 2^14; its GEMMs run on the FP6 matrix cores.
  * The accumulation slab is k_slab terms (a multiple of 128, at most 2^24):
  * every stored plane value lies within r = floor(sqrt(2^24 / k_slab)), so
  * each FP32 accumulator stays exact (eq. "ov-accgen"); a longer k runs in

@@ -67,7 +67,8 @@ Dims dims_of(const ozemu::Plan& p, int64_t m, int64_t n, int64_t k) {
 
 bool is_fp(const ozemu::Plan& p) { return p.format != OZEMU_INT8; }
 
-// bytes of a float plane row of k_pad values
+// bytes of a float plane row of k_pad values (FP6 in the FP8 layout: 24
+// bytes of codes and 8 zero bytes per 32 values)
 int64_t fp_row_bytes(const ozemu::Plan& p, int64_t k_pad) {
     return p.format == OZEMU_E2M1 ? k_pad / 2 : k_pad;
 }
@@ -347,8 +348,9 @@ ozemu_status ozemu_plan_create_fp(ozemu_plan* out, int format, int gemms, int64_
                                   int scaling) {
     if (!out) return fail(OZEMU_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
-    if (format != OZEMU_E4M3 && format != OZEMU_E2M1)
-        return fail(OZEMU_ERR_UNSUPPORTED, "float plans are built for OZEMU_E4M3 and OZEMU_E2M1");
+    if (format != OZEMU_E4M3 && format != OZEMU_E2M3 && format != OZEMU_E2M1)
+        return fail(OZEMU_ERR_UNSUPPORTED,
+                    "float plans are built for OZEMU_E4M3, OZEMU_E2M3 and OZEMU_E2M1");
     ozemu_plan p = new (std::nothrow) ozemu_plan_s;
     if (!p) return fail(OZEMU_ERR_INVALID_ARG, "out of host memory");
     std::string err = ozemu::build_plan_fp(p->p, format, gemms, k_slab, scaling);

@@ -302,18 +302,41 @@ __device__ __forceinline__ void load_tables(const uint8_t* tables, int bytes, ui
     __syncthreads();
 }
 
-// Codes of 16 consecutive entries into plane p at (row, h): 16 bytes (FP8)
-// or 8 bytes (FP4).
-template <bool kFp4>
+// Codes of 16 consecutive entries (h a multiple of 16) into plane p at
+// (row, h): 16 bytes (FP8), 8 bytes (FP4, two codes per byte) or 12 bytes
+// (FP6). An FP6 plane has the FP8 layout with each 32-byte half of a 64-entry
+// step holding the 24 bytes of its 32 codes (code i at bits [6 i, 6 i + 6))
+// and 8 zero bytes; the second 16 codes of a half start at byte 12, so they
+// go out as 4 bytes at the end of one 16-byte chunk and 8 bytes plus the
+// zeros into the next (chunks are permuted inside a row).
+template <int kBits>
 __device__ __forceinline__ void store_codes(int8_t* plane, int64_t row, int64_t h, int64_t kb_pad,
                                             const uint8_t* code) {
-    if constexpr (!kFp4) {
+    if constexpr (kBits == 8) {
         uint4 w;
         w.x = code[0] | (code[1] << 8) | (code[2] << 16) | ((uint32_t)code[3] << 24);
         w.y = code[4] | (code[5] << 8) | (code[6] << 16) | ((uint32_t)code[7] << 24);
         w.z = code[8] | (code[9] << 8) | (code[10] << 16) | ((uint32_t)code[11] << 24);
         w.w = code[12] | (code[13] << 8) | (code[14] << 16) | ((uint32_t)code[15] << 24);
         *reinterpret_cast<uint4*>(plane + plane_offset(row, h, kb_pad)) = w;
+    } else if constexpr (kBits == 6) {
+        uint32_t d[3] = {0u, 0u, 0u};
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const uint32_t c = code[q] & 63u;
+            const int bit = 6 * q, w = bit / 32, o = bit % 32;
+            d[w] |= c << o;
+            if (o > 26) d[w + 1] |= c >> (32 - o);
+        }
+        const int64_t base = (h / 64) * 64 + ((h % 64) / 32) * 32;
+        if ((h % 32) == 0) {
+            *reinterpret_cast<uint3*>(plane + plane_offset(row, base, kb_pad)) =
+                make_uint3(d[0], d[1], d[2]);
+        } else {
+            *reinterpret_cast<uint32_t*>(plane + plane_offset(row, base + 12, kb_pad)) = d[0];
+            *reinterpret_cast<uint4*>(plane + plane_offset(row, base + 16, kb_pad)) =
+                make_uint4(d[1], d[2], 0u, 0u);
+        }
     } else {
         uint32_t lo = 0, hi = 0;
 #pragma unroll
@@ -326,13 +349,13 @@ __device__ __forceinline__ void store_codes(int8_t* plane, int64_t row, int64_t 
 
 // A side: thread handles a 16-entry chunk of a row (chunks cross rows as in
 // encode_a). Dynamic LDS: the table blob.
-template <bool kFp4>
+template <int kBits>
 __global__ __launch_bounds__(kEncThreads) void encode_fp_a_kernel(
     FpConsts fc, const uint8_t* tables, int table_bytes, int64_t m, int64_t k, const double* A,
     int64_t lda, const int32_t* shift_a, int64_t m_pad, int64_t k_pad, int8_t* planes) {
     extern __shared__ uint8_t tab[];
     load_tables(tables, table_bytes, tab);
-    const int64_t kb_pad = kFp4 ? k_pad / 2 : k_pad;
+    const int64_t kb_pad = kBits == 4 ? k_pad / 2 : k_pad;
     const int64_t plane_stride = m_pad * kb_pad;
     const int64_t c = (int64_t)blockIdx.x * kChunksPerBlock + threadIdx.x;
     const int64_t cpr = k_pad / kEncVec;
@@ -342,7 +365,7 @@ __global__ __launch_bounds__(kEncThreads) void encode_fp_a_kernel(
     uint8_t code[kEncVec];
     if (i >= m || h >= k) {  // padding: code 0 is +0 in both formats
         for (int q = 0; q < kEncVec; ++q) code[q] = 0;
-        for (int p = 0; p < fc.planes; ++p) store_codes<kFp4>(planes + p * plane_stride, i, h, kb_pad, code);
+        for (int p = 0; p < fc.planes; ++p) store_codes<kBits>(planes + p * plane_stride, i, h, kb_pad, code);
         return;
     }
     Entry ent[kEncVec];
@@ -365,27 +388,27 @@ __global__ __launch_bounds__(kEncThreads) void encode_fp_a_kernel(
         for (int r = 0; r < rank; ++r) {
 #pragma unroll
             for (int q = 0; q < kEncVec; ++q) code[q] = t[cls[q] * rank + r];
-            store_codes<kFp4>(planes + (fc.plane0[ch] + r) * plane_stride, i, h, kb_pad, code);
+            store_codes<kBits>(planes + (fc.plane0[ch] + r) * plane_stride, i, h, kb_pad, code);
         }
     }
 }
 
 // B side: workgroup (bx, by) covers columns 64 bx .. + 63 and K rows
 // 64 by .. + 63; thread t takes column t % 64 over 16 consecutive K.
-template <bool kFp4>
+template <int kBits>
 __global__ __launch_bounds__(kEncThreads) void encode_fp_b_kernel(
     FpConsts fc, const uint8_t* tables, int table_bytes, int64_t k, int64_t n, const double* B,
     int64_t ldb, const int32_t* shift_b, int64_t n_pad, int64_t k_pad, int8_t* planes) {
     extern __shared__ uint8_t tab[];
     load_tables(tables, table_bytes, tab);
-    const int64_t kb_pad = kFp4 ? k_pad / 2 : k_pad;
+    const int64_t kb_pad = kBits == 4 ? k_pad / 2 : k_pad;
     const int64_t plane_stride = n_pad * kb_pad;
     const int64_t j = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
     const int64_t h = (int64_t)blockIdx.y * 64 + (threadIdx.x >> 6) * kEncVec;
     uint8_t code[kEncVec];
     if (j >= n || h >= k) {
         for (int q = 0; q < kEncVec; ++q) code[q] = 0;
-        for (int p = 0; p < fc.planes; ++p) store_codes<kFp4>(planes + p * plane_stride, j, h, kb_pad, code);
+        for (int p = 0; p < fc.planes; ++p) store_codes<kBits>(planes + p * plane_stride, j, h, kb_pad, code);
         return;
     }
     Entry ent[kEncVec];
@@ -407,7 +430,7 @@ __global__ __launch_bounds__(kEncThreads) void encode_fp_b_kernel(
         for (int r = 0; r < rank; ++r) {
 #pragma unroll
             for (int q = 0; q < kEncVec; ++q) code[q] = t[cls[q] * rank + r];
-            store_codes<kFp4>(planes + (fc.plane0[ch] + r) * plane_stride, j, h, kb_pad, code);
+            store_codes<kBits>(planes + (fc.plane0[ch] + r) * plane_stride, j, h, kb_pad, code);
         }
     }
 }
@@ -467,26 +490,27 @@ hipError_t launch_encode_fp(hipStream_t st, const FpConsts& fc, const uint8_t* t
                             int64_t lda, const double* B, int64_t ldb, const int32_t* shift_a,
                             const int32_t* shift_b, int64_t m_pad, int64_t n_pad, int64_t k_pad,
                             int8_t* planes_a, int8_t* planes_b) {
-    const bool fp4 = fc.fmt == 4;
     const size_t lds = (size_t)table_bytes;
-    if (m_pad > 0 && k_pad > 0) {
-        dim3 grid((unsigned)((m_pad * (k_pad / kEncVec) + kChunksPerBlock - 1) / kChunksPerBlock));
-        if (fp4)
-            encode_fp_a_kernel<true><<<grid, dim3(kEncThreads), lds, st>>>(
+    auto run = [&](auto bits_tag) {
+        constexpr int kBits = decltype(bits_tag)::value;
+        if (m_pad > 0 && k_pad > 0) {
+            dim3 grid((unsigned)((m_pad * (k_pad / kEncVec) + kChunksPerBlock - 1) /
+                                 kChunksPerBlock));
+            encode_fp_a_kernel<kBits><<<grid, dim3(kEncThreads), lds, st>>>(
                 fc, tables, table_bytes, m, k, A, lda, shift_a, m_pad, k_pad, planes_a);
-        else
-            encode_fp_a_kernel<false><<<grid, dim3(kEncThreads), lds, st>>>(
-                fc, tables, table_bytes, m, k, A, lda, shift_a, m_pad, k_pad, planes_a);
-    }
-    if (n_pad > 0 && k_pad > 0) {
-        dim3 grid((unsigned)(n_pad / 64), (unsigned)(k_pad / 64));
-        if (fp4)
-            encode_fp_b_kernel<true><<<grid, dim3(kEncThreads), lds, st>>>(
+        }
+        if (n_pad > 0 && k_pad > 0) {
+            dim3 grid((unsigned)(n_pad / 64), (unsigned)(k_pad / 64));
+            encode_fp_b_kernel<kBits><<<grid, dim3(kEncThreads), lds, st>>>(
                 fc, tables, table_bytes, k, n, B, ldb, shift_b, n_pad, k_pad, planes_b);
-        else
-            encode_fp_b_kernel<false><<<grid, dim3(kEncThreads), lds, st>>>(
-                fc, tables, table_bytes, k, n, B, ldb, shift_b, n_pad, k_pad, planes_b);
-    }
+        }
+    };
+    if (fc.fmt == 4)
+        run(std::integral_constant<int, 4>{});
+    else if (fc.fmt == 2)
+        run(std::integral_constant<int, 6>{});
+    else
+        run(std::integral_constant<int, 8>{});
     return hipGetLastError();
 }
 

@@ -121,7 +121,12 @@ __device__ __forceinline__ void barrier_no_fence() {
 // with FP32 accumulators: FP8 E4M3 (32 bytes per lane, one instruction per
 // 64-byte K step) and FP4 E2M1 (16 bytes per lane, two per step, read as
 // INT8 is).
-enum Fmt : int { kI8 = 0, kF8 = 1, kF4 = 2 };
+enum Fmt : int { kI8 = 0, kF8 = 1, kF4 = 2, kF6 = 3 };
+// FP6 E2M3 uses the FP8 tile, K pipeline and 32-byte fragments: a lane's 32
+// values are 24 bytes of 6-bit codes (value i at bits [6 i, 6 i + 6) of the
+// first six dwords), followed by 8 bytes the instruction does not read.
+template <int F>
+constexpr int mfma_fmt() { return F == kF4 ? 4 : F == kF6 ? 2 : 0; }
 
 // Epilogue of a float-channel product: residues z (uint16, row stride
 // n_pad) of the tile receive (z + lbar (W mod m)) mod m, or that value
@@ -215,7 +220,7 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
     using yes = std::integral_constant<bool, true>;
     using no = std::integral_constant<bool, false>;
 
-    if constexpr (F != kF8) {
+    if constexpr (F != kF8 && F != kF6) {
     v4i xa[2][kFN], yb[2][kFM];
     auto read_frags = [&](int buf, int t, int kk) {
         const int8_t* stage = lds + ring(t) * kDStage;
@@ -325,7 +330,7 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
 #pragma unroll
             for (int a = 0; a < kFM; ++a)
                 acc[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                    xa[b], yb[a], acc[a][b], 0, 0, 0, 0, 0, 0);
+                    xa[b], yb[a], acc[a][b], mfma_fmt<F>(), mfma_fmt<F>(), 0, 0, 0, 0);
             if constexpr (kNext) xa[b] = frag8(nxt + offB + b * 32 * kDBK);
         }
         if constexpr (kNext) {
@@ -610,6 +615,8 @@ hipError_t launch_fp_gemm(hipStream_t st, const FpGemmArgs& g, int fmt) {
     if (blocks <= 0) return hipSuccess;
     if (fmt == 4)
         fp_gemm_kernel<kF4><<<dim3((unsigned)blocks), dim3(kThreads), 0, st>>>(g);
+    else if (fmt == 2)
+        fp_gemm_kernel<kF6><<<dim3((unsigned)blocks), dim3(kThreads), 0, st>>>(g);
     else
         fp_gemm_kernel<kF8><<<dim3((unsigned)blocks), dim3(kThreads), 0, st>>>(g);
     return hipGetLastError();

@@ -222,7 +222,7 @@ __host__ __device__ __forceinline__ uint32_t trunc_residue(uint64_t mant, int sh
 struct FpConsts {
     int n;       // channels
     int planes;  // sum of ranks
-    int fmt;     // MFMA operand format: 0 FP8 E4M3, 4 FP4 E2M1
+    int fmt;     // MFMA operand format: 0 FP8 E4M3, 2 FP6 E2M3, 4 FP4 E2M1
     int es;      // plane value v is stored as v * 2^-es
     uint32_t m[kMaxModuli];
     uint32_t mu[kMaxModuli];

@@ -354,6 +354,8 @@ bool alphabet_of(int format, Alphabet& a) {
     bool fn;
     if (format == 1) {  // E4M3
         E = 4, M = 3, fn = true, a.es = 9;
+    } else if (format == 2) {  // E2M3 (FP6: no infinities or NaN)
+        E = 2, M = 3, fn = false, a.es = 3;
     } else if (format == 3) {  // E2M1
         E = 2, M = 1, fn = false, a.es = 1;
     } else {
@@ -595,7 +597,7 @@ std::string build_plan_fp(Plan& p, int format, int gemms, int64_t k_slab, int sc
     FpConsts& f = p.fp;
     f = FpConsts{};
     f.n = (int)chosen.size();
-    f.fmt = format == 1 ? 0 : 4;
+    f.fmt = format == 1 ? 0 : format == 2 ? 2 : 4;  // MFMA operand format codes
     f.es = al.es;
     p.tables.clear();
     int plane = 0;

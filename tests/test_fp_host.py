@@ -12,7 +12,8 @@ from paper_2609_37693_amd import _lib  # noqa: E402
 @pytest.mark.parametrize("fmt,gemms,k_slab", [("E4M3", 0, 2 ** 14), ("E4M3", 40, 2 ** 14),
                                               ("E2M1", 0, 2 ** 14),
                                               ("E2M1", 40, 2 ** 14), ("E2M1", 24, 2 ** 14),
-                                              ("E4M3", 20, 2 ** 16)])
+                                              ("E4M3", 20, 2 ** 16), ("E2M3", 0, 2 ** 14),
+                                              ("E2M3", 36, 2 ** 14), ("E2M3", 0, 2 ** 12)])
 def test_library_channels_equal_oracle(fmt, gemms, k_slab):
     plan = oz.Plan(format=fmt, gemms=gemms, k_slab=k_slab)
     if gemms == 0:
@@ -22,9 +23,15 @@ def test_library_channels_equal_oracle(fmt, gemms, k_slab):
     assert plan.channels() == [tuple(mb) for mb in want]
 
 
+def test_e2m3_plan_is_e4m3_configuration_at_2_14():
+    """E2M3 and E4M3 share their usable alphabet within radius 32 at
+    K_t = 2**14, so the library picks the same channels for both."""
+    a = oz.Plan(format="E2M3", gemms=0, k_slab=2 ** 14)
+    b = oz.Plan(format="E4M3", gemms=0, k_slab=2 ** 14)
+    assert a.channels() == b.channels() and a.gemms() == 30
+
+
 def test_float_plan_errors():
-    with pytest.raises(_lib.OzemuError):  # FP6 is not built
-        oz.Plan(format="E2M3", gemms=30)
     with pytest.raises(_lib.OzemuError):  # slab not a multiple of 128
         oz.Plan(format="E4M3", gemms=30, k_slab=1000)
     with pytest.raises(_lib.OzemuError):

@@ -1,5 +1,5 @@
-"""GPU parity of the float-channel path (FP8 E4M3 and FP4 E2M1 matrix
-cores, FP32 accumulation) against oracle/fp_scheme.py, bitwise, through
+"""GPU parity of the float-channel path (FP8 E4M3, FP6 E2M3 and FP4 E2M1
+matrix cores, FP32 accumulation) against oracle/fp_scheme.py, bitwise, through
 the C-ABI: ragged shapes, several channel sets, slabs, an accumulator
 driven to exactly 2**24, and sampled entries of the 16384-cubed workload."""
 import numpy as np
@@ -30,7 +30,7 @@ def _config(fmt, gemms, k_slab):
 
 
 CASES = [("E4M3", 30, "W"), ("E4M3", 0, "F53"), ("E4M3", 0, "W"), ("E2M1", 40, "W"),
-         ("E2M1", 24, "W")]
+         ("E2M1", 24, "W"), ("E2M3", 0, "W"), ("E2M3", 36, "F53"), ("E2M3", 22, "W")]
 SHAPES = [(256, 256, 256), (300, 257, 129), (5, 700, 3), (513, 260, 1100), (1, 1, 1)]
 
 
@@ -49,7 +49,7 @@ def test_fp_dgemm_matches_oracle(fmt, gemms, mode, shape):
     assert np.array_equal(host(C), ref)
 
 
-@pytest.mark.parametrize("fmt,gemms", [("E4M3", 30), ("E2M1", 40)])
+@pytest.mark.parametrize("fmt,gemms", [("E4M3", 30), ("E2M1", 40), ("E2M3", 30)])
 def test_fp_slabs_and_special_values(fmt, gemms):
     """K = 20000 runs in two slabs of 16384 terms whose residues add
     modulo m; a NaN row, a zero column and an infinite column as in the
@@ -80,14 +80,15 @@ def _value_for_class(target, beta, m):
     raise AssertionError("no value")
 
 
-def test_fp8_accumulator_at_lambda_is_exact():
+@pytest.mark.parametrize("fmt", ["E4M3", "E2M3"])
+def test_accumulator_at_lambda_is_exact(fmt):
     """Every entry of A' and B' congruent to 32 modulo 49, whose one-limb
     plane value is 32 = floor(sqrt(2**24 / 2**14)): each accumulator of
     that channel sums 2**14 products 32 * 32 = 2**24 exactly on the FP8
-    unit; the whole product must equal the oracle bitwise."""
+    (or FP6) unit; the whole product must equal the oracle bitwise."""
     import torch
-    plan = oz.Plan(format="E4M3", gemms=0, k_slab=16384)
-    cfg = _config("E4M3", 0, 16384)
+    plan = oz.Plan(format=fmt, gemms=0, k_slab=16384)
+    cfg = _config(fmt, 0, 16384)
     assert 49 in [mb.m for mb in cfg]
     K = 16384
     ba, bb = plan.kept_bits(K)
@@ -98,15 +99,15 @@ def test_fp8_accumulator_at_lambda_is_exact():
     A[1::2] *= -1.0  # signs vary by row, magnitudes stay at the radius
     C = oz.dgemm(dev(A), dev(B), plan)
     torch.cuda.synchronize()
-    ref = fs.emulate_fp(A, B, "E4M3", cfg, 16384, "W")["C"]
+    ref = fs.emulate_fp(A, B, fmt, cfg, 16384, "W")["C"]
     assert np.array_equal(host(C), ref)
     assert np.array_equal(host(C), A @ B)  # small integers: the exact product
 
 
-@pytest.mark.parametrize("fmt,gemms", [("E4M3", 0), ("E2M1", 0)])
+@pytest.mark.parametrize("fmt,gemms", [("E4M3", 0), ("E2M1", 0), ("E2M3", 0)])
 def test_fp_16384_sampled_parity_and_error(fmt, gemms):
     """The float workload, m = n = k = 16384, phi = 1, at the window
-    configurations (Q = 30 for E4M3, 62 for E2M1): sampled rows x columns
+    configurations (Q = 30 for E4M3 and E2M3, 62 for E2M1): sampled rows x columns
     bitwise equal to the oracle (kept bits depend on K and the modulus
     product only); the exact scaled error is reported and bounded by 2**-46
     (53/54 kept bits at this K; 2**-50 takes a few more GEMMs)."""
