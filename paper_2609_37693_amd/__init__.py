@@ -26,7 +26,7 @@ def version() -> str:
 
 class Plan:
     """An emulation plan: modulus set (INT8) or limb channels of a float
-    alphabet (format "E4M3" or "E2M1", ``gemms`` GEMMs, slabs of ``k_slab``
+    alphabet (format "E4M3", "E2M3" or "E2M1", ``gemms`` GEMMs, slabs of ``k_slab``
     terms; gemms = 0 takes the least count for the window at K = k_slab),
     scaling mode, CRT constants (host)."""
 
