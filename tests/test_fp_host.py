@@ -13,7 +13,7 @@ from paper_2609_37693_amd import _lib  # noqa: E402
                                               ("E2M1", 0, 2 ** 14),
                                               ("E2M1", 40, 2 ** 14), ("E2M1", 24, 2 ** 14),
                                               ("E4M3", 20, 2 ** 16), ("E2M3", 0, 2 ** 14),
-                                              ("E2M3", 36, 2 ** 14), ("E2M3", 0, 2 ** 12)])
+                                              ("E2M3", 36, 2 ** 14), ("E2M3", 24, 2 ** 15)])
 def test_library_channels_equal_oracle(fmt, gemms, k_slab):
     plan = oz.Plan(format=fmt, gemms=gemms, k_slab=k_slab)
     if gemms == 0:
