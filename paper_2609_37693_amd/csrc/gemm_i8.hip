@@ -568,32 +568,56 @@ __global__ __launch_bounds__(kThreads) void group_gemm_kernel(GroupArgs g) {
         const int x = (x0 + d) & (kXcds - 1);
         const int32_t* pre = g.prefix + (kGTiles + x) * (g.count + 1);
         const int32_t total = pre[g.count];
-        for (;;) {
-            if (threadIdx.x == 0) next = atomicAdd(g.counter + x, 1);
-            __syncthreads();
-            const int32_t w = __builtin_amdgcn_readfirstlane(next);
-            __syncthreads();
-            if (w >= total) break;
-            const int q = group_find(pre, g.count, w);
-            const GProblem& P = g.probs[g.order[q]];
-            const int tiles_m = (int)(P.m_pad / kBM), tiles_n = (int)(P.n_pad / kBN);
-            const int64_t T = (int64_t)tiles_m * tiles_n;
-            const ModConsts& mc = g.mods[P.plan];
-            int first, cnt;
-            xcd_moduli(mc.n, x, q, first, cnt);
-            const int64_t local = w - pre[q];  // < cnt * T
-            const int l = first + kXcds * (int)(local / T);
+        if (threadIdx.x == 0) next = atomicAdd(g.counter + x, 1);
+        __syncthreads();
+        int32_t w = __builtin_amdgcn_readfirstlane(next);
+        __syncthreads();
+        // The problem of the previous item, kept while the items stay in it
+        // (they come in runs of whole moduli), so that most items need no
+        // table reads before their tile starts.
+        int q = -1, first = 0, tiles_m = 1, tiles_n = 1;
+        int32_t qlo = 0, qhi = 0, T = 1;
+        int64_t m_pad = 0, n_pad = 0, k_pad = 0;
+        const int8_t* pa = nullptr;
+        const int8_t* pb = nullptr;
+        uint8_t* pz = nullptr;
+        const ModConsts* mc = nullptr;
+        while (w < total) {
+            if (q < 0 || w >= qhi) {
+                q = group_find(pre, g.count, w);
+                qlo = pre[q];
+                qhi = pre[q + 1];
+                const GProblem& P = g.probs[g.order[q]];
+                m_pad = P.m_pad;
+                n_pad = P.n_pad;
+                k_pad = P.k_pad;
+                tiles_m = (int)(m_pad / kBM);
+                tiles_n = (int)(n_pad / kBN);
+                T = tiles_m * tiles_n;
+                pa = reinterpret_cast<const int8_t*>(g.ws + P.off_pa);
+                pb = reinterpret_cast<const int8_t*>(g.ws + P.off_pb);
+                pz = reinterpret_cast<uint8_t*>(g.ws + P.off_z);
+                mc = g.mods + P.plan;
+                int cnt;
+                xcd_moduli(mc->n, x, q, first, cnt);
+            }
+            // the next item's index is fetched while this one runs
+            int32_t nxt = 0;
+            if (threadIdx.x == 0) nxt = atomicAdd(g.counter + x, 1);
+            const int32_t local = w - qlo;  // < cnt * T
+            const int l = first + kXcds * (local / T);
             int tm, tn;
             band_tile(local % T, tiles_m, tiles_n, tm, tn);
-            const int8_t* gA = reinterpret_cast<const int8_t*>(g.ws + P.off_pa) +
-                               (int64_t)l * P.m_pad * P.k_pad + (int64_t)tm * kBM * P.k_pad;
-            const int8_t* gB = reinterpret_cast<const int8_t*>(g.ws + P.off_pb) +
-                               (int64_t)l * P.n_pad * P.k_pad + (int64_t)tn * kBN * P.k_pad;
-            uint8_t* gZ = reinterpret_cast<uint8_t*>(g.ws + P.off_z) +
-                          (int64_t)l * P.m_pad * P.n_pad + (int64_t)tm * kBM * P.n_pad +
+            const int8_t* gA = pa + (int64_t)l * m_pad * k_pad + (int64_t)tm * kBM * k_pad;
+            const int8_t* gB = pb + (int64_t)l * n_pad * k_pad + (int64_t)tn * kBN * k_pad;
+            uint8_t* gZ = pz + (int64_t)l * m_pad * n_pad + (int64_t)tm * kBM * n_pad +
                           (int64_t)tn * kBN;
-            gemm_tile<Epi::kMod>(mc.m[l], mc.mu[l], P.k_pad, P.n_pad, gA, gB, gZ, nullptr, nullptr,
+            gemm_tile<Epi::kMod>(mc->m[l], mc->mu[l], k_pad, n_pad, gA, gB, gZ, nullptr, nullptr,
                                  tm, tn, lds);
+            if (threadIdx.x == 0) next = nxt;
+            __syncthreads();
+            w = __builtin_amdgcn_readfirstlane(next);
+            __syncthreads();
         }
     }
 }
