@@ -22,7 +22,7 @@ struct ozemu_plan_s {
 // prefixes, laid out as they are copied to the start of the workspace.
 struct ozemu_group_s {
     int count = 0, nplans = 0, dmax = 2;
-    bool big = false;  // some problem keeps more than 63 bits
+    bool big = false;  // some problem keeps more than kSmallBits bits
     size_t table_bytes = 0, ws_bytes = 0;
     size_t off_probs = 0, off_mods = 0, off_crts = 0, off_prefix = 0, off_order = 0,
            off_counter = 0;
@@ -178,14 +178,14 @@ void kept_bits_of(const ozemu::Plan& p, int64_t k, int& ba, int& bb) {
     if (bb > ozemu::kBetaCap) bb = ozemu::kBetaCap;
 }
 
-// True when some row or column may keep more than 63 bits, so the encoder
-// needs its shift table (the bound mode's bits are decided on the device,
+// True when some row or column may keep more than kSmallBits bits, so the
+// encoder takes its exact form for any shift (with its shift table) (the bound mode's bits are decided on the device,
 // up to kBetaCap).
 bool big_encode(const ozemu::Plan& p, int64_t k) {
     if (p.scaling == OZEMU_SCALE_BOUND) return true;
     int ba, bb;
     kept_bits_of(p, k, ba, bb);
-    return ba > 63 || bb > 63;
+    return ba > ozemu::kSmallBits || bb > ozemu::kSmallBits;
 }
 
 // Scale with all arguments validated; ws may be NULL unless BOUND.
@@ -729,7 +729,7 @@ ozemu_status ozemu_group_create(ozemu_group* out, int count, const ozemu_plan* p
         if (k[p] > 0) kept_bits_of(pl, k[p], ba, bb);
         P.beta_a = ba;
         P.beta_b = bb;
-        P.big = (ba > 63 || bb > 63) ? 1 : 0;
+        P.big = (ba > kSmallBits || bb > kSmallBits) ? 1 : 0;
     }
     ozemu_group g = new (std::nothrow) ozemu_group_s;
     if (!g) return fail(OZEMU_ERR_INVALID_ARG, "out of host memory");
@@ -914,7 +914,7 @@ ozemu_status ozemu_dgemm_fwd_cache(ozemu_plan plan, void* stream, int64_t m, int
     const int64_t ks = cache_k(m, n, k);
     int bx, bw;
     kept_bits_of(p, ks, bx, bw);
-    const bool big = bx > 63 || bw > 63;
+    const bool big = bx > ozemu::kSmallBits || bw > ozemu::kSmallBits;
     using namespace ozemu;
     ozemu_status s = hip_check(launch_scale_rows(st, m, k, X, ldx, shift_x), "scale_rows");
     if (!s) s = hip_check(launch_scale_cols(st, k, n, W, ldw, shift_w), "scale_cols");
@@ -999,7 +999,7 @@ ozemu_status ozemu_dgemm_bwd(ozemu_plan plan, void* stream, int64_t m, int64_t n
     ozemu_status s = hip_check(launch_fill_i32(st, kp, 0, zeros), "zeros");
     if (!s && dx_run) {
         // dX = dY W^T: rows of dY folded by 2^-t, cached W planes transposed
-        const bool big = beta_dx > 63;
+        const bool big = beta_dx > kSmallBits;
         s = hip_check(launch_scale_rows(st, m, n, dY, lddy, s2, shift_w), "scale_rows dY");
         if (!s) s = hip_check(launch_keys_to_shifts(st, m, s2, beta_dx, nullptr), "shifts dY");
         if (!s)
@@ -1015,7 +1015,7 @@ ozemu_status ozemu_dgemm_bwd(ozemu_plan plan, void* stream, int64_t m, int64_t n
     }
     if (!s && dw_run) {
         // dW = X^T dY: columns of dY folded by 2^-s, cached X planes transposed
-        const bool big = beta_dw > 63;
+        const bool big = beta_dw > kSmallBits;
         s = hip_check(launch_scale_cols(st, m, n, dY, lddy, t3, shift_x), "scale_cols dY");
         if (!s) s = hip_check(launch_keys_to_shifts(st, n, t3, beta_dw, nullptr), "shifts dY");
         if (!s)

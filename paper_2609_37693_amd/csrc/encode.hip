@@ -51,13 +51,16 @@ __device__ __forceinline__ Entry make_entry(double x, int32_t shift) {
     return e;
 }
 
-// An entry in the form the INT8 residues use: the two's-complement bytes
-// of A' (of 2^64 - |A'| when A' < 0) and a mask that adds (-2^64) mod m per
-// modulus for those, so that sum_i byte_i 2^(8 i) + correction is congruent
-// to A' modulo every m.
+// An entry in the form the INT8 residues use. With kBig false (at most 62
+// kept bits, |A'| < 2^62): A' as eight signed base-256 digits d_i in
+// [-128, 127], A' = sum_i d_i 2^(8 i): the bytes of A' + 0x8080...80 (two's
+// complement, no wrap since |A'| < 2^62) with their top bits flipped. With
+// kBig true: the bytes of |A'| (of 2^64 - |A'| when A' < 0) and a mask that
+// adds (-2^64) mod m per modulus for negative entries; sh > 0 is applied per
+// modulus.
 struct Entry8 {
     uint32_t lo, hi;
-    uint32_t negm;  // all ones if A' < 0
+    uint32_t negm;  // kBig: all ones if A' < 0
     int sh;
 };
 
@@ -68,14 +71,21 @@ __device__ __forceinline__ Entry8 make_entry8(double x, int32_t shift) {
     const bool neg = e.neg && v != 0;
     const uint64_t w = neg ? (uint64_t)0 - v : v;
     Entry8 r;
-    r.lo = (uint32_t)w;
-    r.hi = (uint32_t)(w >> 32);
-    r.negm = neg ? 0xFFFFFFFFu : 0u;
     r.sh = e.sh;
+    if constexpr (kBig) {
+        r.lo = (uint32_t)w;
+        r.hi = (uint32_t)(w >> 32);
+        r.negm = neg ? 0xFFFFFFFFu : 0u;
+    } else {
+        const uint64_t y = w + 0x8080808080808080ull;
+        r.lo = (uint32_t)y ^ 0x80808080u;
+        r.hi = (uint32_t)(y >> 32) ^ 0x80808080u;
+        r.negm = 0u;
+    }
     return r;
 }
 
-// Balanced residue t - m floor(t / m + 1/2), in [-floor(m/2), ceil(m/2) - 1],
+// Balanced residue t - m floor(t/m + 1/2), in [-floor(m/2), ceil(m/2) - 1],
 // of t < 2^19. With rcp_up = 1/m rounded up, fma(t, rcp_up, 1/2) is never
 // below t/m + 1/2 and exceeds it by less than 1/(8m) + 2^-24, while the
 // distance from t/m + 1/2 up to the next integer is at least 1/(2m) (when
@@ -87,15 +97,30 @@ __device__ __forceinline__ int32_t balanced19(uint32_t t, uint32_t m, float rcp_
 }
 
 // Balanced residue of the entry modulo m_l, as an int32 in [-128, 127]; p2
-// is the LDS table of 2^s mod m_l (kBig only). The two byte dot products
-// sum at most 8 * 255 * 255 + 255 < 2^19.
+// is the LDS table of 2^s mod m_l (kBig only). kBig false: two signed byte
+// dot products with the balanced weights 2^(8 i) mod m (|sum| <= 8 128 127
+// < 2^17) on top of km = a multiple of m in [2^17, 2^17 + m), so t lies in
+// [0, 2^19). kBig true: two unsigned byte dot products sum at most
+// 8 255 255 + 255 < 2^19.
 template <bool kBig>
 __device__ __forceinline__ int32_t entry_residue(const Entry8& e, const ModConsts& mc, int l,
                                                  const uint8_t* p2) {
     const uint32_t m = mc.m[l];
-    uint32_t t = __builtin_amdgcn_udot4(e.lo, mc.w8[l][0], e.negm & mc.c64n[l], false);
-    t = __builtin_amdgcn_udot4(e.hi, mc.w8[l][1], t, false);
-    if (kBig && e.sh > 0) t = mod24(t, m, mc.rcp[l]) * p2[e.sh];  // below 2^16
+    uint32_t t;
+    if constexpr (kBig) {
+        t = __builtin_amdgcn_udot4(e.lo, mc.w8[l][0], e.negm & mc.c64n[l], false);
+        t = __builtin_amdgcn_udot4(e.hi, mc.w8[l][1], t, false);
+        if (e.sh > 0) t = mod24(t, m, mc.rcp[l]) * p2[e.sh];  // below 2^16
+    } else {
+        // weights in VGPRs (copied once per modulus) and km as the scalar
+        // addend of a three-operand dot product: no per-entry copy of km
+        int32_t w0, w1, u;
+        asm("v_mov_b32 %0, %1" : "=v"(w0) : "s"(mc.s8[l][0]));
+        asm("v_mov_b32 %0, %1" : "=v"(w1) : "s"(mc.s8[l][1]));
+        asm("v_dot4_i32_i8 %0, %1, %2, %3" : "=v"(u) : "v"(e.lo), "v"(w0), "s"(mc.km[l]));
+        u = __builtin_amdgcn_sdot4((int32_t)e.hi, w1, u, false);
+        t = (uint32_t)u;
+    }
     return balanced19(t, m, mc.rcp_up[l]);
 }
 
@@ -436,7 +461,7 @@ __global__ __launch_bounds__(kEncThreads) void encode_fp_b_kernel(
 }
 
 // ---- Grouped Reduce ----
-// kBig is chosen for the whole group (the form for kept bits above 63 is
+// kBig is chosen for the whole group (the form for kept bits above 62 is
 // exact for any shift, only slower).
 
 template <bool kBig>

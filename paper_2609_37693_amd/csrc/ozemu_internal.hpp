@@ -13,6 +13,7 @@ constexpr int kMaxDigits = 10;  // 32-bit digits of CRT sums: N * P < 2^(8*32 + 
 constexpr int kChunkBits = 40;  // FP64 chunks of CRT sums with INT8 moduli
 constexpr int kMaxChunks = 7;   // 40-bit chunks of P + 2 bits for at most 32 moduli of <= 2^8
 constexpr int kBetaCap = 127;   // largest kept-bit count of any mode
+constexpr int kSmallBits = 62;  // kept bits up to which Reduce takes signed base-256 digits
 
 // Residue GEMM tiling. Planes are padded to whole tiles, so the GEMM kernel
 // needs no bounds checks; padding entries are zero.
@@ -53,6 +54,8 @@ struct ModConsts {
     uint32_t w8[kMaxModuli][2];   // bytes 2^(8 i) mod m, i = 0..3 and 4..7 (m <= 256)
     float rcp_up[kMaxModuli];     // 1 / m rounded up to FP32
     uint32_t c64n[kMaxModuli];    // (-2^64) mod m
+    uint32_t s8[kMaxModuli][2];   // signed bytes: balanced 2^(8 i) mod m, i = 0..7
+    uint32_t km[kMaxModuli];      // m ceil(2^17 / m)
 };
 
 // t mod m for t < 2^24 and 2 <= m <= 256: t is exact in FP32 and t * rcp

@@ -249,12 +249,16 @@ std::string fill_moduli(Plan& p, const std::vector<int>& ms) {
             const uint64_t c = (uint64_t)((((unsigned __int128)1) << 64) % m);
             p.mod.c64n[l] = (uint32_t)((m - c) % m);
         }
+        p.mod.km[l] = m * (((1u << 17) + m - 1) / m);
+        p.mod.s8[l][0] = p.mod.s8[l][1] = 0;
         p.mod.w8[l][0] = p.mod.w8[l][1] = 0;
         if (m <= 256)
             for (int i = 0; i < 8; ++i) {
                 uint64_t w = 1 % m;
                 for (int b = 0; b < 8 * i; ++b) w = (w * 2) % m;
                 p.mod.w8[l][i / 4] |= (uint32_t)w << (8 * (i % 4));
+                const int64_t bal = (int64_t)w > (int64_t)m / 2 ? (int64_t)w - m : (int64_t)w;
+                p.mod.s8[l][i / 4] |= (uint32_t)(uint8_t)(int8_t)bal << (8 * (i % 4));
             }
         p.crt.m[l] = m;
         p.crt.mu[l] = mu;
