@@ -67,10 +67,11 @@ Dims dims_of(const ozemu::Plan& p, int64_t m, int64_t n, int64_t k) {
 
 bool is_fp(const ozemu::Plan& p) { return p.format != OZEMU_INT8; }
 
-// bytes of a float plane row of k_pad values (FP6 in the FP8 layout: 24
-// bytes of codes and 8 zero bytes per 32 values)
+// bytes of a float plane row of k_pad values (FP6 packed: 48 bytes per 64)
 int64_t fp_row_bytes(const ozemu::Plan& p, int64_t k_pad) {
-    return p.format == OZEMU_E2M1 ? k_pad / 2 : k_pad;
+    if (p.format == OZEMU_E2M1) return k_pad / 2;
+    if (p.format == OZEMU_E2M3) return k_pad / 4 * 3;
+    return k_pad;
 }
 
 struct Layout {

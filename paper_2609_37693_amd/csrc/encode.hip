@@ -329,11 +329,10 @@ __device__ __forceinline__ void load_tables(const uint8_t* tables, int bytes, ui
 
 // Codes of 16 consecutive entries (h a multiple of 16) into plane p at
 // (row, h): 16 bytes (FP8), 8 bytes (FP4, two codes per byte) or 12 bytes
-// (FP6). An FP6 plane has the FP8 layout with each 32-byte half of a 64-entry
-// step holding the 24 bytes of its 32 codes (code i at bits [6 i, 6 i + 6))
-// and 8 zero bytes; the second 16 codes of a half start at byte 12, so they
-// go out as 4 bytes at the end of one 16-byte chunk and 8 bytes plus the
-// zeros into the next (chunks are permuted inside a row).
+// (FP6, packed: code i of a 32-code half at bits [6 i, 6 i + 6) of its 24
+// bytes, units placed by plane_offset6; kb_pad is then the padded K in
+// codes). The first 16 codes of a half fill its unit 0 and the low half of
+// unit 1, the second 16 the high half of unit 1 and unit 2.
 template <int kBits>
 __device__ __forceinline__ void store_codes(int8_t* plane, int64_t row, int64_t h, int64_t kb_pad,
                                             const uint8_t* code) {
@@ -353,14 +352,16 @@ __device__ __forceinline__ void store_codes(int8_t* plane, int64_t row, int64_t 
             d[w] |= c << o;
             if (o > 26) d[w + 1] |= c >> (32 - o);
         }
-        const int64_t base = (h / 64) * 64 + ((h % 64) / 32) * 32;
-        if ((h % 32) == 0) {
-            *reinterpret_cast<uint3*>(plane + plane_offset(row, base, kb_pad)) =
-                make_uint3(d[0], d[1], d[2]);
+        const int64_t s = h >> 6;
+        const int u0 = 3 * (int)((h >> 5) & 1);
+        if ((h & 16) == 0) {
+            *reinterpret_cast<uint2*>(plane + plane_offset6(row, s, u0, kb_pad)) =
+                make_uint2(d[0], d[1]);
+            *reinterpret_cast<uint32_t*>(plane + plane_offset6(row, s, u0 + 1, kb_pad)) = d[2];
         } else {
-            *reinterpret_cast<uint32_t*>(plane + plane_offset(row, base + 12, kb_pad)) = d[0];
-            *reinterpret_cast<uint4*>(plane + plane_offset(row, base + 16, kb_pad)) =
-                make_uint4(d[1], d[2], 0u, 0u);
+            *reinterpret_cast<uint32_t*>(plane + plane_offset6(row, s, u0 + 1, kb_pad) + 4) = d[0];
+            *reinterpret_cast<uint2*>(plane + plane_offset6(row, s, u0 + 2, kb_pad)) =
+                make_uint2(d[1], d[2]);
         }
     } else {
         uint32_t lo = 0, hi = 0;
@@ -380,8 +381,9 @@ __global__ __launch_bounds__(kEncThreads) void encode_fp_a_kernel(
     int64_t lda, const int32_t* shift_a, int64_t m_pad, int64_t k_pad, int8_t* planes) {
     extern __shared__ uint8_t tab[];
     load_tables(tables, table_bytes, tab);
+    // row argument of store_codes (bytes, or codes for FP6) and plane bytes
     const int64_t kb_pad = kBits == 4 ? k_pad / 2 : k_pad;
-    const int64_t plane_stride = m_pad * kb_pad;
+    const int64_t plane_stride = m_pad * (kBits == 6 ? k_pad / 4 * 3 : kb_pad);
     const int64_t c = (int64_t)blockIdx.x * kChunksPerBlock + threadIdx.x;
     const int64_t cpr = k_pad / kEncVec;
     const int64_t i = c / cpr;
@@ -427,7 +429,7 @@ __global__ __launch_bounds__(kEncThreads) void encode_fp_b_kernel(
     extern __shared__ uint8_t tab[];
     load_tables(tables, table_bytes, tab);
     const int64_t kb_pad = kBits == 4 ? k_pad / 2 : k_pad;
-    const int64_t plane_stride = n_pad * kb_pad;
+    const int64_t plane_stride = n_pad * (kBits == 6 ? k_pad / 4 * 3 : kb_pad);
     const int64_t j = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
     const int64_t h = (int64_t)blockIdx.y * 64 + (threadIdx.x >> 6) * kEncVec;
     uint8_t code[kEncVec];

@@ -23,6 +23,7 @@ namespace ozemu {
 
 namespace {
 
+typedef int v2i __attribute__((ext_vector_type(2)));
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 typedef int v8i __attribute__((ext_vector_type(8)));
@@ -122,9 +123,10 @@ __device__ __forceinline__ void barrier_no_fence() {
 // 64-byte K step) and FP4 E2M1 (16 bytes per lane, two per step, read as
 // INT8 is).
 enum Fmt : int { kI8 = 0, kF8 = 1, kF4 = 2, kF6 = 3 };
-// FP6 E2M3 uses the FP8 tile, K pipeline and 32-byte fragments: a lane's 32
-// values are 24 bytes of 6-bit codes (value i at bits [6 i, 6 i + 6) of the
-// first six dwords), followed by 8 bytes the instruction does not read.
+// FP6 E2M3 uses the FP8 tile and K pipeline over packed planes (48 bytes of
+// a row per K step of 64 codes, plane_offset6): a lane's 32 values are 24
+// bytes of 6-bit codes (value i at bits [6 i, 6 i + 6) of the first six
+// dwords of the operand; the last two are not read).
 template <int F>
 constexpr int mfma_fmt() { return F == kF4 ? 4 : F == kF6 ? 2 : 0; }
 
@@ -158,27 +160,35 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
             return (int)((unsigned)t % (unsigned)S);
     };
 
-    // Loads: wave-load R = wave * 8 + p copies kilobyte R % 16 of operand
-    // R / 16's block for the step; lane L moves bytes [16 L, 16 L + 16).
+    // Bytes of a row of one K step (48 for packed FP6, else 64), of one
+    // operand's block of a step, and 1 KB wave loads per wave per step.
+    constexpr int kRowB = (F == kF6) ? kF6StepBytes : kDBK;
+    constexpr int kOpB = kPlaneRows * kRowB;
+    constexpr int kPerSide = kOpB / 1024;
+    constexpr int kLoads = 2 * kPerSide / 4;
+    static_assert(kLoads * 4 * 1024 == 2 * kOpB, "load split");
+    // Loads: wave-load R = wave * kLoads + p copies kilobyte R % kPerSide of
+    // operand R / kPerSide's block for the step; lane L moves bytes
+    // [16 L, 16 L + 16).
     // The LDS destination of a wave-level load is uniform: its offsets are
     // made scalar once, outside the K loop, so each load's M0 comes from
     // scalar arithmetic only.
-    const int8_t* gsrc[kDLoads];
-    int lds_off[kDLoads];
+    const int8_t* gsrc[kLoads];
+    int lds_off[kLoads];
     const int wave_s = __builtin_amdgcn_readfirstlane(wave);
 #pragma unroll
-    for (int p = 0; p < kDLoads; ++p) {
-        const int R = wave_s * kDLoads + p;
-        const int side = R >> 4, r16 = R & 15;
-        gsrc[p] = (side ? gB : gA) + r16 * 1024 + lane * 16;
-        lds_off[p] = side * kBM * kDBK + r16 * 1024;
+    for (int p = 0; p < kLoads; ++p) {
+        const int R = wave_s * kLoads + p;
+        const int side = R / kPerSide, rk = R % kPerSide;
+        gsrc[p] = (side ? gB : gA) + rk * 1024 + lane * 16;
+        lds_off[p] = side * kOpB + rk * 1024;
     }
     auto dma = [&](int t) {
         int8_t* stage = lds + ring(t) * kDStage;
 #pragma unroll
-        for (int p = 0; p < kDLoads; ++p)
+        for (int p = 0; p < kLoads; ++p)
             __builtin_amdgcn_global_load_lds(
-                (const void*)(gsrc[p] + (int64_t)t * (kPlaneRows * kPlaneK)),
+                (const void*)(gsrc[p] + (int64_t)t * kOpB),
                 (lds_ptr_t)(stage + lds_off[p]), 16, 0, 0);
     };
 
@@ -198,21 +208,21 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
     const int offB = kBM * kDBK + (wj * kWaveN + fr) * kDBK;
     const int cofs0 = ((0 + (lane >> 5)) ^ fsw) * 16;
     const int cofs1 = ((2 + (lane >> 5)) ^ fsw) * 16;
-    const int nk = (int)(k_pad / kDBK);
+    const int nk = (int)(k_pad / kRowB);
     const int pre = nk < S - 1 ? nk : S - 1;
     // waits: at the end of step t stage t + 2 must be in LDS; the loads of
     // the stages issued after it may stay in flight
     auto wait_prologue = [&]() {
         if (pre >= 4)
-            __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(2 * kDLoads, 0));
+            __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(2 * kLoads, 0));
         else if (pre == 3)
-            __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(kDLoads, 0));
+            __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(kLoads, 0));
         else
             __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(0, 0));
     };
     auto wait_stages = [&](auto n_tag) {
         constexpr int n = decltype(n_tag)::value;
-        __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(n * kDLoads, 0));
+        __builtin_amdgcn_s_waitcnt(OZ_WAITCNT(n * kLoads, 0));
     };
     using w0 = std::integral_constant<int, 0>;
     using w1 = std::integral_constant<int, 1>;
@@ -267,7 +277,7 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
         mfma_slice(0);
         if constexpr (kLoad) {
 #pragma unroll
-            for (int i = 0; i < kDLoads; ++i) {
+            for (int i = 0; i < kLoads; ++i) {
                 __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
                 __builtin_amdgcn_sched_group_barrier(0x010, 1, 0);  // global load to LDS
             }
@@ -306,20 +316,37 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
     // fragments after the last MFMA of the step.
     const int c8lo = ((2 * (lane >> 5)) ^ fsw) * 16;
     const int c8hi = ((2 * (lane >> 5) + 1) ^ fsw) * 16;
+    // FP6 (packed): the 24 bytes of a lane's 32 codes are units 3h .. 3h + 2
+    // of its row, unit u at position (u + rot) mod 6 (plane_offset6; the
+    // rows of a 32-row block start at multiples of 32, so rot depends on
+    // lane & 31 only); three 8-byte reads.
+    const int f6rot = ((fr >> 3) ^ (fr >> 4)) & 1;
+    const int u6 = 3 * (lane >> 5);
+    const int p6a = ((u6 + f6rot) % 6) * 8, p6b = ((u6 + 1 + f6rot) % 6) * 8,
+              p6c = ((u6 + 2 + f6rot) % 6) * 8;
+    const int offA8 = (wi * kWaveM + fr) * kRowB;
+    const int offB8 = kOpB + (wj * kWaveN + fr) * kRowB;
     v8i xa[kFN], yb[kFM];
     auto frag8 = [&](const int8_t* base) {
-        const v4i lo = *reinterpret_cast<const v4i*>(base + c8lo);
-        const v4i hi = *reinterpret_cast<const v4i*>(base + c8hi);
-        return (v8i){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+        if constexpr (F == kF6) {
+            const v2i a = *reinterpret_cast<const v2i*>(base + p6a);
+            const v2i b = *reinterpret_cast<const v2i*>(base + p6b);
+            const v2i c = *reinterpret_cast<const v2i*>(base + p6c);
+            return (v8i){a[0], a[1], b[0], b[1], c[0], c[1], 0, 0};
+        } else {
+            const v4i lo = *reinterpret_cast<const v4i*>(base + c8lo);
+            const v4i hi = *reinterpret_cast<const v4i*>(base + c8hi);
+            return (v8i){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+        }
     };
     auto stage_of = [&](int t) { return lds + ring(t) * kDStage; };
     for (int t = 0; t < pre; ++t) dma(t);
     wait_prologue();
     barrier_no_fence();
 #pragma unroll
-    for (int b = 0; b < kFN; ++b) xa[b] = frag8(stage_of(0) + offB + b * 32 * kDBK);
+    for (int b = 0; b < kFN; ++b) xa[b] = frag8(stage_of(0) + offB8 + b * 32 * kRowB);
 #pragma unroll
-    for (int a = 0; a < kFM; ++a) yb[a] = frag8(stage_of(0) + offA + a * 32 * kDBK);
+    for (int a = 0; a < kFM; ++a) yb[a] = frag8(stage_of(0) + offA8 + a * 32 * kRowB);
     auto step8 = [&](int t, auto load_tag, auto next_tag, auto wait_tag) {
         constexpr bool kLoad = decltype(load_tag)::value;
         constexpr bool kNext = decltype(next_tag)::value;
@@ -331,15 +358,15 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
             for (int a = 0; a < kFM; ++a)
                 acc[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
                     xa[b], yb[a], acc[a][b], mfma_fmt<F>(), mfma_fmt<F>(), 0, 0, 0, 0);
-            if constexpr (kNext) xa[b] = frag8(nxt + offB + b * 32 * kDBK);
+            if constexpr (kNext) xa[b] = frag8(nxt + offB8 + b * 32 * kRowB);
         }
         if constexpr (kNext) {
 #pragma unroll
-            for (int a = 0; a < kFM; ++a) yb[a] = frag8(nxt + offA + a * 32 * kDBK);
+            for (int a = 0; a < kFM; ++a) yb[a] = frag8(nxt + offA8 + a * 32 * kRowB);
         }
         if constexpr (kLoad) {
 #pragma unroll
-            for (int i = 0; i < kDLoads; ++i) {
+            for (int i = 0; i < kLoads; ++i) {
                 __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
                 __builtin_amdgcn_sched_group_barrier(0x010, 1, 0);  // global load to LDS
             }
@@ -540,9 +567,9 @@ __global__ __launch_bounds__(kThreads) void fp_gemm_kernel(FpGemmArgs g) {
     band_tile(t, tiles_m, tiles_n, tm, tn);
     const int64_t pl = g.plane[c];
     const int8_t* gA = g.pa + pl * g.m_pad * g.kb_pad + (int64_t)tm * kBM * g.kb_pad +
-                       (g.kb_begin / kDBK) * (kPlaneRows * kPlaneK);
+                       g.kb_begin * kPlaneRows;
     const int8_t* gB = g.pb + pl * g.n_pad * g.kb_pad + (int64_t)tn * kBN * g.kb_pad +
-                       (g.kb_begin / kDBK) * (kPlaneRows * kPlaneK);
+                       g.kb_begin * kPlaneRows;
     FpEpi fe;
     fe.z = g.z + (int64_t)g.chan[c] * g.m_pad * g.n_pad + (int64_t)tm * kBM * g.n_pad +
            (int64_t)tn * kBN;

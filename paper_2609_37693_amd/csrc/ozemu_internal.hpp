@@ -35,6 +35,22 @@ __host__ __device__ __forceinline__ int64_t plane_offset(int64_t row, int64_t h,
     return ((tr * (k_pad >> 6) + ks) * 256 + r) * 64 + ((c ^ ((r >> 2) & 3)) << 4) + (h & 15);
 }
 
+// Packed FP6 planes: a K step of 64 codes is 48 bytes of a row, six 8-byte
+// units; the block of (row tile, step) is 256 rows x 48 bytes at
+// ((tile * steps) + step) * 12288, row r at 48 r in it, and unit u at
+// position (u + rot(r)) mod 6 with rot(r) = ((r >> 3) ^ (r >> 4)) & 1, so
+// that the 8-byte fragment reads of 32 consecutive rows spread over the LDS
+// banks. Byte offset of unit u (0..5) of step s of a row; k_pad in codes.
+constexpr int kF6StepBytes = 48;
+__host__ __device__ __forceinline__ int64_t plane_offset6(int64_t row, int64_t s, int u,
+                                                        int64_t k_pad) {
+    const int64_t tr = row >> 8;
+    const int r = (int)(row & 255);
+    const int rot = ((r >> 3) ^ (r >> 4)) & 1;
+    const int pos = (u + rot) % 6;
+    return ((tr * (k_pad >> 6) + s) * 256 + r) * kF6StepBytes + 8 * pos;
+}
+
 // Row/column key for the exponent scan: frexp exponent of the largest
 // magnitude, or these sentinels.
 constexpr int32_t kKeyZero = INT32_MIN + 1;
