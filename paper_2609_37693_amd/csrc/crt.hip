@@ -115,14 +115,19 @@ __device__ __forceinline__ double finish_one(const CrtConsts& cc, int64_t* acc, 
 // up, the bits below p folded into the lowest (they are only a sticky
 // bit), are rounded at rb to nearest even in integer arithmetic and scaled
 // exactly.
-template <int D, int KC>
+template <int D, int KC, int CB>
 __device__ __forceinline__ double finish_chunks(const CrtConsts& cc, const double* s, int sc) {
+    // f is within 2^-34 of S / P for INT8 moduli (S / P < 2^13) and within
+    // 2^-26 for float channels (S / P < 2^21); the fast path keeps clear of
+    // that by a factor of 16 or more
+    constexpr double kTau = CB == kChunkBits ? 0x1p-30 : 0x1p-20;
+    constexpr double kUnit = (double)(1ull << CB), kInvUnit = 1.0 / kUnit;
     double f = 0.0;
 #pragma unroll
     for (int k = 0; k < KC; ++k) f = __builtin_fma(s[k], cc.R40[k], f);
     const double q = rint(f);
     const double e = f - q;
-    const bool fast = fabs(e) >= 0x1p-30 && fabs(e) <= 0.5 - 0x1p-30;
+    const bool fast = fabs(e) >= kTau && fabs(e) <= 0.5 - kTau;
     const double sg = (fast && e < 0.0) ? -1.0 : 1.0;
     const double qs = q * sg;
     uint64_t ch[KC + 1];
@@ -131,21 +136,22 @@ __device__ __forceinline__ double finish_chunks(const CrtConsts& cc, const doubl
     for (int k = 0; k < KC; ++k) {
         // |t| < 2^53: exact
         const double t = __builtin_fma(-qs, cc.P40[k], s[k] * sg) + carry;
-        carry = floor(t * 0x1p-40);
-        const double d = __builtin_fma(-carry, 0x1p40, t);  // [0, 2^40)
+        carry = floor(t * kInvUnit);
+        const double d = __builtin_fma(-carry, kUnit, t);  // [0, 2^CB)
         const double hi = floor(d * 0x1p-32);
         const double lo = __builtin_fma(-hi, 0x1p32, d);
         ch[k] = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
     }
     bool neg = carry < 0.0;  // false on the fast path
-    ch[KC] = neg ? 0xFFFFFFFFFFull : 0ull;  // sign extension of the chunk form
+    ch[KC] = neg ? (1ull << CB) - 1ull : 0ull;  // sign extension of the chunk form
     // 32-bit words of sg X (two's complement over 32 D bits)
     uint32_t x[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        const int k0 = (32 * j) / kChunkBits, o = 32 * j - kChunkBits * k0;
+        const int k0 = (32 * j) / CB, o = 32 * j - CB * k0;
         uint64_t v = ch[k0] >> o;
-        if (kChunkBits - o < 32) v |= ch[k0 + 1] << (kChunkBits - o);
+        if (CB - o < 32) v |= ch[k0 + 1] << (CB - o);
+        if (CB - o + CB < 32) v |= ch[k0 + 2] << (CB - o + CB);
         x[j] = (uint32_t)v;
     }
     if (fast) {
@@ -268,44 +274,93 @@ __device__ __forceinline__ void reconstruct_body(const CrtConsts& cc, int64_t m,
             if (si == kShiftNonFinite || tj[c] == kShiftNonFinite)
                 out[c] = __builtin_nan("");
             else
-                out[c] = finish_chunks<D, KC>(cc, sk[c], si + tj[c]);
+                out[c] = finish_chunks<D, KC, kChunkBits>(cc, sk[c], si + tj[c]);
         }
     } else {
-        // float-channel moduli (up to 2^16): u_l = (z_l inv_l) mod m_l and
-        // S = sum_l u_l M_l in 32-bit digits, each term below 2^48
-        int64_t acc[kPerThread][D];
-        double f[kPerThread];
+        constexpr int KC = (32 * D + kChunkBitsFp - 1) / kChunkBitsFp;
+        bool done = false;
+        if constexpr (KC <= kMaxChunks) {
+            if (cc.kc > 0) {
+                // float-channel moduli (below 2^16): S = sum_l z_l N_l in
+                // 30-bit chunks, exact in FP64 (a product is below 2^46, a
+                // chunk's sum over at most 32 channels below 2^51); loads as
+                // in the INT8 form
+                constexpr int kBatch = 16;
+                double sk[kPerThread][KC];
 #pragma unroll
-        for (int c = 0; c < kPerThread; ++c) f[c] = 0.0;
+                for (int c = 0; c < kPerThread; ++c)
 #pragma unroll
-        for (int c = 0; c < kPerThread; ++c)
+                    for (int k = 0; k < KC; ++k) sk[c][k] = 0.0;
+                for (int l0 = 0; l0 < cc.n; l0 += kBatch) {
+                    uint2 word[kBatch];
 #pragma unroll
-            for (int d = 0; d < D; ++d) acc[c][d] = 0;
-        for (int l = 0; l < cc.n; ++l) {
-            uint32_t zv[kPerThread];
-            const uint2 w2 = *reinterpret_cast<const uint2*>(zp + (int64_t)l * plane);
-            zv[0] = w2.x & 0xFFFFu;
-            zv[1] = w2.x >> 16;
-            zv[2] = w2.y & 0xFFFFu;
-            zv[3] = w2.y >> 16;
-            const uint32_t ml = cc.m[l], mu = cc.mu[l], inv = cc.inv[l];
-            const double rcp = cc.rcp[l];
+                    for (int b = 0; b < kBatch; ++b) {
+                        const int l = (l0 + b < cc.n) ? l0 + b : cc.n - 1;
+                        word[b] = *reinterpret_cast<const uint2*>(zp + (int64_t)l * plane);
+                    }
 #pragma unroll
-            for (int c = 0; c < kPerThread; ++c) {
-                const uint64_t u = barrett32(zv[c] * inv, ml, mu);
-                f[c] += (double)u * rcp;
+                    for (int b = 0; b < kBatch; ++b) {
+                        const bool live = l0 + b < cc.n;
+                        const int l = live ? l0 + b : cc.n - 1;
+                        const uint32_t w0 = live ? word[b].x : 0u, w1 = live ? word[b].y : 0u;
+                        const double z[kPerThread] = {(double)(w0 & 0xFFFFu), (double)(w0 >> 16),
+                                                      (double)(w1 & 0xFFFFu), (double)(w1 >> 16)};
 #pragma unroll
-                for (int d = 0; d < D; ++d) acc[c][d] += (int64_t)(u * cc.Ml[l][d]);
+                        for (int c = 0; c < kPerThread; ++c)
+#pragma unroll
+                            for (int k = 0; k < KC; ++k)
+                                sk[c][k] = __builtin_fma(z[c], cc.N40[l][k], sk[c][k]);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < kPerThread; ++c) {
+                    out[c] = 0.0;
+                    if (j0 + c >= n) continue;
+                    if (si == kShiftNonFinite || tj[c] == kShiftNonFinite)
+                        out[c] = __builtin_nan("");
+                    else
+                        out[c] = finish_chunks<D, KC, kChunkBitsFp>(cc, sk[c], si + tj[c]);
+                }
+                done = true;
             }
         }
+        if (!done) {
+            // too many chunks: u_l = (z_l inv_l) mod m_l and S = sum_l u_l M_l
+            // in 32-bit digits, each term below 2^48
+            int64_t acc[kPerThread][D];
+            double f[kPerThread];
 #pragma unroll
-        for (int c = 0; c < kPerThread; ++c) {
-            out[c] = 0.0;
-            if (j0 + c >= n) continue;
-            if (si == kShiftNonFinite || tj[c] == kShiftNonFinite)
-                out[c] = __builtin_nan("");
-            else
-                out[c] = finish_one<D>(cc, acc[c], f[c], si + tj[c]);
+            for (int c = 0; c < kPerThread; ++c) f[c] = 0.0;
+#pragma unroll
+            for (int c = 0; c < kPerThread; ++c)
+#pragma unroll
+                for (int d = 0; d < D; ++d) acc[c][d] = 0;
+            for (int l = 0; l < cc.n; ++l) {
+                uint32_t zv[kPerThread];
+                const uint2 w2 = *reinterpret_cast<const uint2*>(zp + (int64_t)l * plane);
+                zv[0] = w2.x & 0xFFFFu;
+                zv[1] = w2.x >> 16;
+                zv[2] = w2.y & 0xFFFFu;
+                zv[3] = w2.y >> 16;
+                const uint32_t ml = cc.m[l], mu = cc.mu[l], inv = cc.inv[l];
+                const double rcp = cc.rcp[l];
+#pragma unroll
+                for (int c = 0; c < kPerThread; ++c) {
+                    const uint64_t u = barrett32(zv[c] * inv, ml, mu);
+                    f[c] += (double)u * rcp;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) acc[c][d] += (int64_t)(u * cc.Ml[l][d]);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < kPerThread; ++c) {
+                out[c] = 0.0;
+                if (j0 + c >= n) continue;
+                if (si == kShiftNonFinite || tj[c] == kShiftNonFinite)
+                    out[c] = __builtin_nan("");
+                else
+                    out[c] = finish_one<D>(cc, acc[c], f[c], si + tj[c]);
+            }
         }
     }
     double* crow = C + i * ldc + j0;

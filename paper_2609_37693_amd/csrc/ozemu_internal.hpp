@@ -10,7 +10,8 @@ namespace ozemu {
 
 constexpr int kMaxModuli = 32;  // moduli per plan
 constexpr int kMaxDigits = 10;  // 32-bit digits of CRT sums: N * P < 2^(8*32 + 5)
-constexpr int kChunkBits = 40;  // FP64 chunks of CRT sums with INT8 moduli
+constexpr int kChunkBits = 40;    // FP64 chunks of CRT sums with INT8 moduli
+constexpr int kChunkBitsFp = 30;  // ... and with float-channel moduli (below 2^16)
 constexpr int kMaxChunks = 7;   // 40-bit chunks of P + 2 bits for at most 32 moduli of <= 2^8
 constexpr int kBetaCap = 127;   // largest kept-bit count of any mode
 constexpr int kSmallBits = 62;  // kept bits up to which Reduce takes signed base-256 digits
@@ -134,9 +135,12 @@ struct CrtConsts {
     uint32_t Ml[kMaxModuli][kMaxDigits];
     uint32_t P[kMaxDigits];
     uint32_t half[kMaxDigits];  // floor((P - 1) / 2)
-    // INT8 moduli: N_l = inv_l M_l (below P) and P in 40-bit chunks held
-    // exactly in FP64, and 2^(40 k) / P rounded to FP64
+    // N_l = inv_l M_l (below P) and P in chunks of cb bits (kChunkBits for
+    // INT8 moduli, kChunkBitsFp for float channels) held exactly in FP64,
+    // and 2^(cb k) / P rounded to FP64; kc chunks (0: too many for the
+    // chunk form, float channels then take 32-bit digits)
     int kc;
+    int cb;
     double N40[kMaxModuli][kMaxChunks];
     double P40[kMaxChunks];
     double R40[kMaxChunks];

@@ -201,11 +201,11 @@ std::string build_plan(Plan& p, int format, const std::vector<int>& moduli_in, i
     return fill_moduli(p, ms);
 }
 
-// Bits [40 c, 40 c + 40) of a big integer.
-static uint64_t chunk40(const BigU& x, int c) {
+// Bits [cb c, cb c + cb) of a big integer.
+static uint64_t chunk_of(const BigU& x, int c, int cb) {
     uint64_t v = 0;
-    for (int b = 0; b < kChunkBits; ++b) {
-        const int bit = kChunkBits * c + b;
+    for (int b = 0; b < cb; ++b) {
+        const int bit = cb * c + b;
         if (bit / 32 < BigU::cap && ((x.d[bit / 32] >> (bit % 32)) & 1u)) v |= 1ull << b;
     }
     return v;
@@ -273,19 +273,24 @@ std::string fill_moduli(Plan& p, const std::vector<int>& ms) {
         if (m == 1 || inv == 0) return "internal: no inverse";
         p.crt.inv[l] = inv;
         for (int i = 0; i < kMaxDigits; ++i) p.crt.Ml[l][i] = Ml.d[i];
-        // N_l = inv_l M_l < m_l M_l = P, in 40-bit chunks
+        // N_l = inv_l M_l < m_l M_l = P, in chunks of cb bits
         BigU Nl = Ml;
         Nl.mul_small(inv);
-        for (int c = 0; c < kMaxChunks; ++c) p.crt.N40[l][c] = (double)chunk40(Nl, c);
+        const int cb = p.format == 0 ? kChunkBits : kChunkBitsFp;
+        for (int c = 0; c < kMaxChunks; ++c) p.crt.N40[l][c] = (double)chunk_of(Nl, c, cb);
     }
-    p.crt.kc = (p.p_bits + 2 + kChunkBits - 1) / kChunkBits;
-    if (p.mod.m[0] <= 256 && p.crt.kc > kMaxChunks) return "modulus product too large";
+    p.crt.cb = p.format == 0 ? kChunkBits : kChunkBitsFp;  // INT8 plans: format 0
+    p.crt.kc = (p.p_bits + 2 + p.crt.cb - 1) / p.crt.cb;
+    if (p.crt.kc > kMaxChunks) {
+        if (p.format == 0) return "modulus product too large";
+        p.crt.kc = 0;  // float channels: 32-bit digits instead
+    }
     {
         double Pd = 0;  // P to within a few ulps
         for (int i = BigU::cap - 1; i >= 0; --i) Pd = Pd * 4294967296.0 + p.P.d[i];
         for (int c = 0; c < kMaxChunks; ++c) {
-            p.crt.P40[c] = (double)chunk40(p.P, c);
-            p.crt.R40[c] = std::ldexp(1.0 / Pd, kChunkBits * c);
+            p.crt.P40[c] = (double)chunk_of(p.P, c, p.crt.cb);
+            p.crt.R40[c] = std::ldexp(1.0 / Pd, p.crt.cb * c);
         }
     }
     BigU half = p.P;
