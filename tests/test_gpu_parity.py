@@ -318,3 +318,22 @@ def test_reconstruct_crt_edge_values(moduli):
             got = C[i, j]
             assert got == want and np.signbit(got) == np.signbit(want), (i, j, xs[j], row_shifts[i])
     assert np.isnan(C[:, n - 1]).all()
+
+
+@pytest.mark.parametrize("nmod,shape", [(17, (130, 90, 64)), (17, (70, 65, 100)),
+                                        (17, (300, 257, 256)), (18, (65, 70, 8192))])
+def test_kept_bits_at_the_reduce_threshold(nmod, shape):
+    """Plans keeping 62 bits (signed-digit Reduce, |A'| up to 2^62 - 2^10
+    here) and 63 bits (the exact form), with rows and columns at their
+    largest magnitude of either sign: bitwise equal to the oracle."""
+    m, n, k = shape
+    plan = oz.Plan(num_moduli=nmod, scaling="W")
+    A, B = _inputs(m, n, k, 0.5, 9)
+    big = 1.0 - 2.0 ** -52
+    A[0, :] = -big
+    A[1, ::2] = big
+    B[:, 0] = -big
+    B[::3, 1] = big
+    C = host(oz.dgemm(dev(A), dev(B), plan))
+    ref = scheme.emulate(A, B, plan.moduli(), "W", keep=False)["C"]
+    assert np.array_equal(C, ref)
