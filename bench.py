@@ -168,6 +168,55 @@ def exact_scaled_error(C, A, B, rows, cols):
     return worst
 
 
+def _ldexp_exact(X, e):
+    """X * 2**e elementwise (e an integer tensor broadcasting against X), in
+    two power-of-two steps so that neither factor leaves the FP64 range; exact
+    whenever the intermediate and the result are normal or the result is the
+    truncation of a representable value."""
+    import torch
+    h = torch.div(e, 2, rounding_mode="floor")
+    return X * torch.pow(2.0, h.to(torch.float64)) * torch.pow(2.0, (e - h).to(torch.float64))
+
+
+def certified_error_bound(A, B, C, beta_a, beta_b):
+    """Certified per-entry bound on |C - AB| / (|A||B|) over the whole matrix.
+
+    Valid for C = RN(A'B' 2^-(s_i+t_j)) with A' = trunc(A 2^s), B' =
+    trunc(B 2^t) and the shifts of the definition: s_i = beta_a - e_i, e_i
+    the frexp exponent of row i's largest magnitude (0 for a zero row),
+    likewise t_j over the columns of B (Sec. V-A, phases 1 and 4). With
+    Ahat = A' 2^-s and dA = A - Ahat (both exact in FP64, dA holds the bits
+    of A below 2^-s_i), AB - Ahat Bhat = dA B + Ahat dB, so
+
+        |C - AB| <= |dA||B| + |Ahat||dB| + 2^-53 |C|.
+
+    The three products of nonnegative matrices are FP64 GEMMs with relative
+    error at most gamma_k = k u / (1 - k u), u = 2^-53, whatever the
+    summation order: numerators are raised by that factor and the
+    denominator |A||B| lowered. Returns (bound tensor, s, t); entries whose
+    row of A or column of B is zero get 0 when C is 0 there, inf otherwise.
+    """
+    import torch
+    k = A.shape[1]
+    u = 2.0 ** -53
+    gam = k * u / (1.0 - k * u)
+    ra = A.abs().amax(dim=1) if k else torch.zeros(A.shape[0], dtype=A.dtype, device=A.device)
+    cb = B.abs().amax(dim=0) if k else torch.zeros(B.shape[1], dtype=B.dtype, device=B.device)
+    s = torch.where(ra > 0, beta_a - torch.frexp(ra).exponent, 0).to(torch.int64)
+    t = torch.where(cb > 0, beta_b - torch.frexp(cb).exponent, 0).to(torch.int64)
+    Ah = _ldexp_exact(torch.trunc(_ldexp_exact(A, s[:, None])), -s[:, None])
+    Bh = _ldexp_exact(torch.trunc(_ldexp_exact(B, t[None, :])), -t[None, :])
+    num = (A - Ah).abs() @ B.abs()
+    num += Ah.abs() @ (B - Bh).abs()
+    num *= (1.0 + 2.0 * gam) * (1.0 + u)
+    num += C.abs() * (u * (1.0 + u))
+    den = (A.abs() @ B.abs()) * (1.0 - gam)
+    pos = den > 0
+    bound = torch.where(pos, num / torch.where(pos, den, 1.0),
+                        torch.where(C == 0, 0.0, float("inf")))
+    return bound, s, t
+
+
 def sweep_main(args):
     """The 8192^3 emulated DGEMM for every moduli count and phi in the
     lists: whole-call time, the exact scaled error over sampled rows x
@@ -529,6 +578,18 @@ def main():
     rel_fro = float(torch.linalg.norm(C - ref) / torch.linalg.norm(ref))
     absAB = A.abs() @ B.abs()
     scaled_vs_native = float(torch.max((C - ref).abs() / absAB))
+    del absAB
+    # certified bound on every entry (valid for the shifts of the definition,
+    # checked against the library's own)
+    certified = None
+    shifts_ok = None
+    if args.scaling != "G":
+        ba, bb = plan.kept_bits(n)
+        bound, s_def, t_def = certified_error_bound(A, B, C, ba, bb)
+        shifts_ok = bool(torch.equal(s_def, sa.to(torch.int64)) and
+                         torch.equal(t_def, sb.to(torch.int64)))
+        certified = float(bound.max())
+        del bound
 
     out = {
         "metric": "emulated DGEMM TFLOP/s vs native FP64 MFMA at 8192^3, at <=2^-50 scaled error",
@@ -560,6 +621,8 @@ def main():
         "speedup_vs_native": (native_ms / ms) if native_ms else None,
         "rel_frobenius_vs_native": rel_fro,
         "max_scaled_diff_vs_native": scaled_vs_native,
+        "certified_max_scaled_error": certified,
+        "shifts_match_definition": shifts_ok,
         "wall_s_timed": wall,
     }
     if not args.no_cpu_baseline:

@@ -40,3 +40,61 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode != 0
     assert "one GPU" in r.stderr
+
+
+@pytest.mark.parametrize("phi,shape,nm,seed,cap", [(0.5, (12, 10, 40), 10, 4, -30),
+                                                   (4.0, (9, 11, 64), 12, 5, -24),
+                                                   (0.5, (7, 6, 300), 16, 6, -50)])
+def test_certified_bound_covers_exact_errors(phi, shape, nm, seed, cap):
+    """bench.py's whole-matrix bound is an upper bound of the exact scaled
+    error on every entry of the oracle's product, with the oracle's shifts,
+    and stays within the entrywise bound of Sec. V-D's error analysis (it
+    is not vacuous)."""
+    torch = pytest.importorskip("torch")
+    from oracle import moduli, scheme
+    m, n, k = shape
+    A, B = operand_pair(m, n, k, phi, seed)
+    A[3] = 0.0
+    B[:, 4] = 0.0
+    ms = moduli.best_coprime_set(nm)
+    ba, bb = scheme.kept_bits("W", moduli.product(ms), k)
+    r = scheme.emulate(A, B, ms, "W")
+    C = r["C"]
+    bound, s, t = bench.certified_error_bound(torch.from_numpy(A), torch.from_numpy(B),
+                                              torch.from_numpy(C), ba, bb)
+    assert np.array_equal(s.numpy(), r["s"]) and np.array_equal(t.numpy(), r["t"])
+    b = bound.numpy()
+    err = exact.scaled_errors(C, A, B)
+    assert np.all(np.isfinite(b)) and np.all(b >= err)
+    assert np.all(b[3] == 0) and np.all(b[:, 4] == 0)
+    # the a priori entrywise bound: truncation below 2^(1 - beta) of each
+    # row's (column's) largest magnitude, plus the final rounding
+    amax = np.abs(A).max(axis=1)[:, None]
+    bmax = np.abs(B).max(axis=0)[None, :]
+    den = np.abs(A) @ np.abs(B)
+    pri = (2.0 ** (1 - ba) * amax * np.abs(B).sum(axis=0)[None, :] +
+           2.0 ** (1 - bb) * bmax * np.abs(A).sum(axis=1)[:, None] +
+           2.0 ** (2 - ba - bb) * k * amax * bmax + 2.0 ** -53 * np.abs(C))
+    nz = den > 0
+    assert np.all(b[nz] <= 1.001 * pri[nz] / den[nz])
+    assert b[nz].max() < 2.0 ** cap
+
+
+def test_certified_bound_misses_a_wrong_rounding():
+    """The bound holds only for the correctly rounded product: a C two ulps
+    away at one entry of a product with no truncation exceeds it there."""
+    torch = pytest.importorskip("torch")
+    from oracle import moduli, scheme
+    rng = np.random.default_rng(7)
+    A = rng.integers(-1000, 1000, (5, 9)).astype(np.float64)
+    B = rng.integers(-1000, 1000, (9, 4)).astype(np.float64)
+    ms = moduli.best_coprime_set(12)
+    ba, bb = scheme.kept_bits("W", moduli.product(ms), 9)
+    C = scheme.emulate(A, B, ms, "W")["C"]
+    assert np.array_equal(C, A @ B)  # small integers: exact
+    bound, _, _ = bench.certified_error_bound(torch.from_numpy(A), torch.from_numpy(B),
+                                              torch.from_numpy(C), ba, bb)
+    Cw = C.copy()
+    Cw[2, 1] = np.nextafter(np.nextafter(C[2, 1], np.inf), np.inf)
+    err = exact.scaled_errors(Cw, A, B)
+    assert err[2, 1] > bound.numpy()[2, 1]

@@ -249,6 +249,31 @@ def test_full_size_sampled_parity_and_error():
     assert err <= 2.0 ** -50, err
 
 
+def test_full_size_certified_bound():
+    """The bench workload over the whole matrix: the Scale phase's shifts
+    equal the definition's (frexp exponents of every row and column maximum)
+    and the certified bound (|dA||B| + |Ahat||dB| + 2^-53 |C|) / (|A||B|),
+    valid for the correctly rounded product that the sampled and small-size
+    parity tests check bit for bit, is at most 2**-50 on every entry."""
+    import os
+    import sys
+    import torch
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    n = 8192
+    A, B = operand_pair(n, n, n, 0.5, 0)
+    plan = oz.Plan(num_moduli=16, scaling="W")
+    dA, dB = dev(A), dev(B)
+    del A, B
+    C = oz.dgemm(dA, dB, plan)
+    sa, sb = oz.scale(dA, dB, plan)
+    ba, bb = plan.kept_bits(n)
+    bound, s, t = bench.certified_error_bound(dA, dB, C, ba, bb)
+    assert torch.equal(s, sa.to(torch.int64)) and torch.equal(t, sb.to(torch.int64))
+    worst = float(bound.max())
+    assert worst <= 2.0 ** -50, worst
+
+
 @pytest.mark.parametrize("shape,mode,nmod", [((4100, 300, 200), "W", 14), ((6000, 50, 70), "G", 16),
                                              ((4352, 257, 129), "F53", 16)])
 def test_tall_products_match_oracle(shape, mode, nmod):
