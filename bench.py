@@ -128,7 +128,15 @@ def cpu_baseline(A, B, moduli, mode, rows):
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count()
+    # native FP64 DGEMM on the same host (numpy's BLAS), 1024 rows of C
+    r2 = min(1024, A.shape[0])
+    A2 = np.ascontiguousarray(A[:r2])
+    A2 @ B
+    t1 = time.perf_counter()
+    A2 @ B
+    dt2 = time.perf_counter() - t1
     return {"value": 2.0 * rows * n * k / dt / 1e12, "unit": "TFLOP/s", "cores": cores,
+            "native_cpu_dgemm_tflops": 2.0 * r2 * n * k / dt2 / 1e12,
             "kind": "oracle",
             "sample": "rows 0..%d of C at %dx%dx%d (%s, %d moduli): %.1f s on %s; BLAS uses "
                       "all cores, the rest of the oracle one" % (rows, rows, n, k, mode,

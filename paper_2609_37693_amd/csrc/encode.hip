@@ -86,17 +86,23 @@ __device__ __forceinline__ Entry8 make_entry8(double x, int32_t shift) {
 }
 
 // Balanced residue t - m floor(t/m + 1/2), in [-floor(m/2), ceil(m/2) - 1],
-// of t < 2^19. With rcp_up = 1/m rounded up, fma(t, rcp_up, 1/2) is never
-// below t/m + 1/2 and exceeds it by less than 1/(8m) + 2^-24, while the
-// distance from t/m + 1/2 up to the next integer is at least 1/(2m) (when
-// m divides 2t + m, the value is itself an integer and is kept): the
-// truncated sum is floor(t/m + 1/2) exactly.
+// of t < 2^19, returned in the low byte of the result (two's complement;
+// the upper bytes are not part of the value). With rcp_up strictly above
+// 1/m (by at most one FP32 ulp), t rcp_up exceeds t/m by less than
+// 2^19 2^-23 / m = 1/(16 m), while t/m lies at least 1/(2m) from every
+// half-integer it is not equal to, and above t/m a tie t/m = k + 1/2 moves
+// up: fma(t, rcp_up, 1.5 2^23), rounded once to the unit grid of
+// [2^23, 2^24), is 1.5 2^23 + q with q = floor(t/m + 1/2). Its low 24 bits
+// are 2^22 + q (bit 23 is the exponent's low bit, 0), so one 24-bit
+// multiply-add gives t - q m - 2^22 m, whose low byte is that of t - q m
+// (2^22 m is a multiple of 256). Checked on the CPU for every m <= 256 and
+// every t < 2^19.
 __device__ __forceinline__ int32_t balanced19(uint32_t t, uint32_t m, float rcp_up) {
-    const uint32_t q = (uint32_t)__builtin_fmaf((float)t, rcp_up, 0.5f);
-    return (int32_t)t + __mul24((int32_t)q, -(int32_t)m);
+    const float x = __builtin_fmaf((float)t, rcp_up, 12582912.0f);
+    return (int32_t)t + __mul24(__builtin_bit_cast(int32_t, x), -(int32_t)m);
 }
 
-// Balanced residue of the entry modulo m_l, as an int32 in [-128, 127]; p2
+// Balanced residue of the entry modulo m_l, in the low byte of the int32; p2
 // is the LDS table of 2^s mod m_l (kBig only). kBig false: two signed byte
 // dot products with the balanced weights 2^(8 i) mod m (|sum| <= 8 128 127
 // < 2^17) on top of km = a multiple of m in [2^17, 2^17 + m), so t lies in

@@ -243,8 +243,9 @@ std::string fill_moduli(Plan& p, const std::vector<int>& ms) {
             p.mod.w12[l][i] = (uint16_t)w;
         }
         {
+            // strictly above 1/m: the next FP32 value up when 1/m is exact
             float r = 1.0f / (float)m;
-            if ((double)r * (double)m < 1.0) r = std::nextafter(r, 1.0f);  // exact test
+            if ((double)r * (double)m <= 1.0) r = std::nextafter(r, 1.0f);  // exact test
             p.mod.rcp_up[l] = r;
             const uint64_t c = (uint64_t)((((unsigned __int128)1) << 64) % m);
             p.mod.c64n[l] = (uint32_t)((m - c) % m);
