@@ -176,10 +176,15 @@ __device__ __forceinline__ void fill_p2(const ModConsts& mc, uint8_t* p2) {
 // row, 256 consecutive chunks per workgroup (crossing rows when k_pad is
 // short), so every thread has work for any K.
 constexpr int64_t kChunksPerBlock = kEncThreads;
+static_assert(kChunksPerBlock == 256 && kEncVec == 16 && kPlaneK == 64, "encode_a tile map");
 
-// Chunk c of the A planes: row i = c / (k_pad / 16), columns [h, h + 16).
-// Padding rows and columns get zeros without residue work. p2: LDS table
-// (kBig only).
+// Chunk c of the A planes (16 entries of a row): groups of 256 chunks (one
+// workgroup) cover tiles of 64 rows x 64 columns, k_pad / 64 tiles per band
+// of 64 rows; chunk t of a group is row t / 4 of its tile, columns
+// 16 (t % 4) .. + 15. A 64-row slice of a plane block is 4 KB in one piece
+// (plane_offset), so each modulus' stores of a workgroup fill one
+// contiguous 4 KB region. Padding rows and columns get zeros without
+// residue work. p2: LDS table (kBig only).
 template <bool kBig, bool kFold>
 __device__ __forceinline__ void encode_a_body(const ModConsts& mc, int64_t m, int64_t k,
                                               const double* A, int64_t lda,
@@ -187,9 +192,11 @@ __device__ __forceinline__ void encode_a_body(const ModConsts& mc, int64_t m, in
                                               int64_t m_pad, int64_t k_pad, int8_t* planes,
                                               int64_t c, uint8_t* p2) {
     fill_p2<kBig>(mc, p2);
-    const int64_t cpr = k_pad / kEncVec;
-    const int64_t i = c / cpr;
-    const int64_t h = (c % cpr) * kEncVec;
+    const int64_t tiles_k = k_pad / kPlaneK;
+    const int64_t tile = c >> 8;
+    const int t = (int)(c & 255);
+    const int64_t i = (tile / tiles_k) * 64 + (t >> 2);
+    const int64_t h = (tile % tiles_k) * kPlaneK + (t & 3) * kEncVec;
     if (i >= m_pad) return;
     const int64_t plane_stride = m_pad * k_pad;
     int8_t* out = planes + plane_offset(i, h, k_pad);
