@@ -110,7 +110,10 @@ __device__ __forceinline__ double finish_one(const CrtConsts& cc, int64_t* acc, 
 // into 40-bit chunks in [0, 2^40), which give the 32-bit words of |X|.
 // Otherwise X itself is formed, its last carry (-1 or 0) is the sign, the
 // words are complemented when negative, and the exact fallback of
-// finish_one applies. The rounding position is rb = max(L - 53, sc - 1074)
+// finish_one applies. On the fast path the rounding is done in FP64 from
+// the leading digits (below), except at an exact tie of the first 53 bits
+// or for results below 2^-1021. The exact rounding position is
+// rb = max(L - 53, sc - 1074)
 // for the bit length L of |X|: the 64 bits of |X| from p = max(rb - 2, 0)
 // up, the bits below p folded into the lowest (they are only a sticky
 // bit), are rounded at rb to nearest even in integer arithmetic and scaled
@@ -130,16 +133,56 @@ __device__ __forceinline__ double finish_chunks(const CrtConsts& cc, const doubl
     const bool fast = fabs(e) >= kTau && fabs(e) <= 0.5 - kTau;
     const double sg = (fast && e < 0.0) ? -1.0 : 1.0;
     const double qs = q * sg;
-    uint64_t ch[KC + 1];
+    double dg[KC];
     double carry = 0.0;
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
         // |t| < 2^53: exact
         const double t = __builtin_fma(-qs, cc.P40[k], s[k] * sg) + carry;
         carry = floor(t * kInvUnit);
-        const double d = __builtin_fma(-carry, kUnit, t);  // [0, 2^CB)
-        const double hi = floor(d * 0x1p-32);
-        const double lo = __builtin_fma(-hi, 0x1p32, d);
+        dg[k] = __builtin_fma(-carry, kUnit, t);  // [0, 2^CB)
+    }
+    if (fast) {
+        // |X| = sum_k dg_k 2^(CB k) >= 0 (nonzero: |X| > tau P). With j its
+        // top nonzero digit, V = top 2^CB + nxt holds its leading 2 CB (if
+        // dg_j >= 2^(53 - CB)) or 3 CB bits (else top = dg_j 2^CB + dg_j-1,
+        // exact below 2^53), at unit 2^unit; V >= 2^53, so hi = RN(V) has
+        // an ulp of at least 2 and its exact remainder e1 (Fast2Sum) is an
+        // integer. Unless |e1| is exactly half an ulp, the digits below V
+        // (worth less than one unit) cannot move the rounding: hi 2^unit
+        // is |X| rounded to 53 bits, and scaling it is exact while the
+        // result stays at or above 2^-1021 (the binade above the smallest
+        // normal, so that no rounding at the subnormal spacing differs) or
+        // overflows to infinity. Ties and tiny results take the exact path.
+        double a = 0.0, b = 0.0, c = 0.0;
+        int j = -1;
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            const bool nz = dg[k] != 0.0;
+            j = nz ? k : j;
+            a = nz ? dg[k] : a;
+            b = nz ? (k >= 1 ? dg[k >= 1 ? k - 1 : 0] : 0.0) : b;
+            c = nz ? (k >= 2 ? dg[k >= 2 ? k - 2 : 0] : 0.0) : c;
+        }
+        const bool low = a < (double)(1ull << (53 - CB));
+        const double top = low ? __builtin_fma(a, kUnit, b) : a;
+        const double nxt = low ? c : b;
+        const int unit = CB * (low ? j - 2 : j - 1);
+        const double big = top * kUnit;
+        const double hi = big + nxt;
+        const double e1 = nxt - (hi - big);
+        const int eh = __builtin_amdgcn_frexp_exp(hi);  // hi = m 2^eh, m in [1/2, 1)
+        const bool tie = fabs(e1) == ldexp(1.0, eh - 54);
+        if (j >= 0 && !tie && eh + unit - sc >= -1020) {
+            const double r = ldexp(hi, unit - sc);
+            return sg < 0.0 ? -r : r;
+        }
+    }
+    uint64_t ch[KC + 1];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        const double hi = floor(dg[k] * 0x1p-32);
+        const double lo = __builtin_fma(-hi, 0x1p32, dg[k]);
         ch[k] = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
     }
     bool neg = carry < 0.0;  // false on the fast path

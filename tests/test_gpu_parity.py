@@ -300,7 +300,8 @@ def test_reconstruct_crt_edge_values(moduli):
     the balanced range +-(P-1)/2 (where the estimate of the nearest multiple
     of P may be off by one), values next to P 2^-30 and P/2 - P 2^-30 (where
     the sign is or is not read from the estimate), rounding ties at 2^53,
-    2^54, 2^64 and 2^100, and random values; row shifts that give normal,
+    2^54, 2^64 and 2^100 and at bit positions around the 40-bit chunk
+    boundaries (with their neighbours), and random values; row shifts that give normal,
     subnormal, zero and infinite results; a column with the non-finite
     marker gives NaN. Bitwise equal to the oracle's one rounding of
     X 2^-(s_i + t_j). The default set holds 256 (P even), the other only
@@ -319,6 +320,16 @@ def test_reconstruct_crt_edge_values(moduli):
           half - e30, half - e30 - 1, half - e30 + 1, half - e31,
           2 ** 53 + 1, 2 ** 53 + 3, 2 ** 54 + 2, 2 ** 54 + 6, 2 ** 64 + 2 ** 11,
           2 ** 64 + 3 * 2 ** 11, 2 ** 100 + 2 ** 47, 2 ** 100 + 2 ** 47 + 1]
+    # exact ties of the 53-bit rounding and their neighbours at bit
+    # positions around the 40-bit chunk boundaries, and leading chunks just
+    # below and above 2^13
+    for pos in (1, 12, 13, 26, 27, 39, 40, 41, 52, 53, 66, 70):
+        for t in (2 ** 52 + 5, 2 ** 52 + 4, 2 ** 53 - 1):
+            x = t * 2 ** (pos + 1) + 2 ** pos
+            xs += [x, x - 1, x + 1]
+    xs += [2 ** 93 - 1, 2 ** 93, 2 ** 93 + 2 ** 40 + 1, 2 ** 52 + 1, 2 ** 53 - 1,
+           2 ** 92 + 2 ** 39, 2 ** 120 + 2 ** 67 + 2 ** 66]
+    xs = [x for x in xs if x <= half]
     xs = xs + [-x for x in xs if x]
     rng = np.random.default_rng(11)
     xs += [int(v) for v in rng.integers(-2 ** 62, 2 ** 62, 8)]
