@@ -1,0 +1,137 @@
+"""CPU checks of the integer and rounding identities that the HIP kernels
+rely on, restated in exact integer arithmetic (no GPU, no kernel code):
+
+* Reduce: the balanced residue t - m floor(t/m + 1/2) of t < 2^19 is the
+  low byte of t - m (low 24 bits of the FP32 word fma(t, r, 1.5 2^23)),
+  r = 1/m rounded strictly up to FP32, for every m <= 256 and every t.
+* GEMM epilogue: for an INT32 accumulator w, t = w + (w >> 16)(c16 - 2^16)
+  (c16 = 2^16 mod m), the 24-bit multiply-add with fma(t, 1/m, 1.5 2^23)
+  and two packed 16-bit unsigned-min corrections give w mod m in [0, m),
+  for every m <= 256 on the extremes and a random sample of w.
+* Reconstruct: rounding |X| = sum_k d_k 2^(40 k) (or 2^(30 k)) to FP64
+  from its leading digits with a Fast2Sum remainder equals the correctly
+  rounded value whenever the fast path accepts it (no exact tie of the
+  53-bit rounding, result at or above 2^-1021)."""
+import math
+import random
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+C_MAGIC = 12582912  # 1.5 2^23
+
+
+def _f32_parts(x):
+    """(M, E) with x = M 2^E exactly, M a 24-bit integer (FP32 x > 0)."""
+    fr, ex = math.frexp(float(np.float32(x)))
+    return int(fr * 2 ** 24), ex - 24
+
+
+def _rne_shift(num, s):
+    """Round num / 2^s to the nearest integer, ties to even (numpy int64)."""
+    q = num >> s
+    rem = num - (q << s)
+    half = np.int64(1) << (s - 1)
+    up = (rem > half) | ((rem == half) & ((q & 1) == 1))
+    return q + up
+
+
+def _mul24(a, b):
+    """v_mul_i32_i24: signed low 24 bits of each, low 32 bits of the product."""
+    a24 = ((a & 0xFFFFFF) ^ 0x800000) - 0x800000
+    b24 = ((b & 0xFFFFFF) ^ 0x800000) - 0x800000
+    return (a24 * b24) & 0xFFFFFFFF
+
+
+def _rcp_up(m):
+    r = np.float32(1.0) / np.float32(m)
+    if float(r) * m <= 1.0:
+        r = np.nextafter(r, np.float32(1.0))
+    return r
+
+
+def test_reduce_residue_from_magic_fma_every_m_and_t():
+    t = np.arange(1 << 19, dtype=np.int64)
+    for m in range(2, 257):
+        M, E = _f32_parts(_rcp_up(m))
+        q = _rne_shift(t * M, -E)  # fma(t, r, 1.5 2^23) - 1.5 2^23, exactly
+        low24 = (0x400000 + q) & 0xFFFFFF
+        r32 = (t + _mul24(low24, -m)) & 0xFFFFFFFF
+        want = t - m * ((2 * t + m) // (2 * m))
+        assert np.array_equal(r32 & 0xFF, want & 0xFF), m
+        assert want.min() >= -(m // 2) and want.max() <= (m + 1) // 2 - 1
+
+
+def test_gemm_epilogue_mod_every_m_sampled_w():
+    rng = np.random.default_rng(3)
+    w = np.concatenate([rng.integers(-2 ** 31, 2 ** 31, 1 << 16, dtype=np.int64),
+                        np.array([-2 ** 31, -2 ** 31 + 1, -1, 0, 1, 2 ** 31 - 1,
+                                  -65536, 65535, 65536, -65537], dtype=np.int64)])
+    for m in range(2, 257):
+        c16 = 65536 % m
+        t = w + (w >> 16) * (c16 - 65536)  # one 24-bit multiply-add on the GPU
+        assert np.abs(t).max() < 2 ** 24
+        M, E = _f32_parts(np.float32(1.0) / np.float32(m))
+        q = _rne_shift(t * M, -E)
+        low24 = (0x400000 + q) & 0xFFFFFF
+        r = (t + _mul24(low24, -m)) & 0xFFFF
+        v = np.minimum(r, (r + m) & 0xFFFF)
+        v = np.minimum(v, (v - m) & 0xFFFF)
+        assert np.array_equal(v, np.mod(w, m)), m
+
+
+def _exact_rn(X, sc):
+    try:
+        return float(Fraction(X) / Fraction(2) ** sc)
+    except OverflowError:
+        return math.inf
+
+
+def _fast_round(X, sc, CB, KC):
+    dg = [float((X >> (CB * k)) & ((1 << CB) - 1)) for k in range(KC)]
+    a = b = c = 0.0
+    j = -1
+    for k in range(KC):
+        if dg[k] != 0.0:
+            j, a = k, dg[k]
+            b = dg[k - 1] if k >= 1 else 0.0
+            c = dg[k - 2] if k >= 2 else 0.0
+    if j < 0:
+        return None
+    unit_f = float(1 << CB)
+    low = a < 2.0 ** (53 - CB)
+    top = a * unit_f + b if low else a
+    nxt = c if low else b
+    unit = CB * (j - 2 if low else j - 1)
+    big = top * unit_f
+    hi = big + nxt
+    e1 = nxt - (hi - big)
+    assert Fraction(big) + Fraction(nxt) - Fraction(hi) == Fraction(e1)  # Fast2Sum is exact
+    eh = math.frexp(hi)[1]
+    if abs(e1) == math.ldexp(1.0, eh - 54) or eh + unit - sc < -1020:
+        return None
+    try:
+        return math.ldexp(hi, unit - sc)
+    except OverflowError:
+        return math.inf
+
+
+@pytest.mark.parametrize("CB,KC,bits", [(40, 4, 137), (30, 7, 200)])
+def test_reconstruct_fast_rounding_is_correct_rounding(CB, KC, bits):
+    rnd = random.Random(CB)
+    taken = 0
+    for _ in range(20000):
+        L = rnd.randint(1, bits)
+        X = rnd.getrandbits(L) | (1 << (L - 1))
+        kind = rnd.random()
+        if L > 60 and kind < 0.3:  # exact ties and their neighbours
+            p = L - 54
+            X = (X >> (p + 1) << (p + 1)) | (1 << p)
+            X += rnd.choice([0, 1, -1])
+        sc = rnd.choice([rnd.randint(-200, 200), rnd.randint(L - 1100, L - 1000), 0])
+        got = _fast_round(X, sc, CB, KC)
+        if got is not None:
+            taken += 1
+            assert got == _exact_rn(X, sc), (X, sc)
+    assert taken > 10000
