@@ -443,28 +443,23 @@ __device__ __forceinline__ void gemm_tile(uint32_t m, uint32_t mu, int64_t k_pad
         }
     } else if constexpr (E == Epi::kMod) {
         uint8_t* sO = reinterpret_cast<uint8_t*>(lds);
-        // w mod m in [0, m) for any INT32 w. t = (w >> 16) (2^16 mod m) +
-        // (w & 0xFFFF), formed as w + (w >> 16) (c16 - 2^16) in one 24-bit
-        // multiply-add, is congruent to w with |t| < 2^15 m + 2^16.
-        // fma(t, rcp, 1.5 2^23) holds 1.5 2^23 + q, q the nearest integer
-        // to t rcp (within 1/2 + 1/m of t / m), in its low mantissa bits, so
-        // t - m x24 (x24 = low 24 bits = 2^22 + q) is t - q m - 2^22 m: its
-        // low 16 bits are r = t - q m in [-m/2 - 1, m/2 + 1] (2^22 m is a
-        // multiple of 2^16). Pairs of r then take two unsigned-min steps in
-        // packed 16-bit arithmetic into [0, m). Exhaustively checked on the
-        // CPU for every m <= 256 and every t.
-        uint32_t c16 = __builtin_amdgcn_readfirstlane(65536u % m);
-        asm volatile("" : "+s"(c16));  // opaque range: keeps the 24-bit multiply-add
-        const int32_t kadj = (int32_t)c16 - 65536;
-        const float rcp = __builtin_bit_cast(
-            float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(uint32_t, 1.0f / (float)m)));
-        const int32_t negm = -(int32_t)m;
+        // w mod m in [0, m) for any INT32 w. x = fma(w, rcp64, 1.5 2^52)
+        // (rcp64 = 1/m in FP64, w rcp64 within 2^-22 / m of w / m) holds
+        // 1.5 2^52 + q, q a nearest integer to w / m, in its low mantissa
+        // bits: its low 32 bits are q in two's complement. One 24-bit
+        // multiply-add w + q24 (2^16 - m) (q24 = the low 24 bits of q) has
+        // the low 16 bits of r = w - q m in [-m/2, m/2]. Pairs of r then take
+        // two unsigned-min steps in packed 16-bit arithmetic into [0, m).
+        // Checked on the CPU for every m <= 256 on the INT32 extremes and a
+        // sample of w.
+        const double rcp64 = 1.0 / (double)m;
+        const uint32_t negm16 = 65536u - m;
         using u16x2 = unsigned short __attribute__((ext_vector_type(2)));
         const u16x2 m2 = {(unsigned short)m, (unsigned short)m};
         auto r16 = [&](int32_t w) -> uint32_t {
-            const int32_t t = __mul24(w >> 16, kadj) + w;
-            const float x = __builtin_fmaf((float)t, rcp, 12582912.0f);
-            return (uint32_t)(t + __mul24(__builtin_bit_cast(int32_t, x), negm));
+            const double x = __builtin_fma((double)w, rcp64, 6755399441055744.0);
+            const uint32_t q = (uint32_t)__builtin_bit_cast(uint64_t, x);
+            return __umul24(q, negm16) + (uint32_t)w;
         };
         auto fix2 = [&](uint32_t lo, uint32_t hi) -> u16x2 {
             u16x2 v = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(hi, lo, 0x05040100u));

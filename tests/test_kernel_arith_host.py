@@ -4,10 +4,11 @@ rely on, restated in exact integer arithmetic (no GPU, no kernel code):
 * Reduce: the balanced residue t - m floor(t/m + 1/2) of t < 2^19 is the
   low byte of t - m (low 24 bits of the FP32 word fma(t, r, 1.5 2^23)),
   r = 1/m rounded strictly up to FP32, for every m <= 256 and every t.
-* GEMM epilogue: for an INT32 accumulator w, t = w + (w >> 16)(c16 - 2^16)
-  (c16 = 2^16 mod m), the 24-bit multiply-add with fma(t, 1/m, 1.5 2^23)
-  and two packed 16-bit unsigned-min corrections give w mod m in [0, m),
-  for every m <= 256 on the extremes and a random sample of w.
+* GEMM epilogue: for an INT32 accumulator w, q from fma(w, 1/m, 1.5 2^52)
+  in FP64 (the low 32 bits of the result), the 24-bit multiply-add
+  w + q24 (2^16 - m) and two packed 16-bit unsigned-min corrections give
+  w mod m in [0, m), for every m <= 256 on the INT32 extremes, exact ties
+  and a random sample of w.
 * Reconstruct: rounding |X| = sum_k d_k 2^(40 k) (or 2^(30 k)) to FP64
   from its leading digits with a Fast2Sum remainder equals the correctly
   rounded value whenever the fast path accepts it (no exact tie of the
@@ -65,20 +66,20 @@ def test_reduce_residue_from_magic_fma_every_m_and_t():
 
 def test_gemm_epilogue_mod_every_m_sampled_w():
     rng = np.random.default_rng(3)
-    w = np.concatenate([rng.integers(-2 ** 31, 2 ** 31, 1 << 16, dtype=np.int64),
-                        np.array([-2 ** 31, -2 ** 31 + 1, -1, 0, 1, 2 ** 31 - 1,
-                                  -65536, 65535, 65536, -65537], dtype=np.int64)])
+    ws = [-2 ** 31, -2 ** 31 + 1, -1, 0, 1, 2 ** 31 - 1, -65536, 65535, 65536, -65537]
+    ws += [int(v) for v in rng.integers(-2 ** 31, 2 ** 31, 400)]
     for m in range(2, 257):
-        c16 = 65536 % m
-        t = w + (w >> 16) * (c16 - 65536)  # one 24-bit multiply-add on the GPU
-        assert np.abs(t).max() < 2 ** 24
-        M, E = _f32_parts(np.float32(1.0) / np.float32(m))
-        q = _rne_shift(t * M, -E)
-        low24 = (0x400000 + q) & 0xFFFFFF
-        r = (t + _mul24(low24, -m)) & 0xFFFF
-        v = np.minimum(r, (r + m) & 0xFFFF)
-        v = np.minimum(v, (v - m) & 0xFFFF)
-        assert np.array_equal(v, np.mod(w, m)), m
+        rcp64 = Fraction(1.0 / m)  # FP64 1/m, exactly
+        # exact ties w / m = k + 1/2 in both signs
+        wm = ws + [k * m + m // 2 for k in (-(2 ** 31) // m + 1, -3, 0, 5, (2 ** 31 - 1) // m - 1)
+                   if m % 2 == 0]
+        for w in wm:
+            q = round(w * rcp64)  # fma(w, rcp64, 1.5 2^52) - 1.5 2^52: one rounding, ties to even
+            q32 = q & 0xFFFFFFFF
+            r = ((q32 & 0xFFFFFF) * (65536 - m) + (w & 0xFFFFFFFF)) & 0xFFFF
+            v = min(r, (r + m) & 0xFFFF)
+            v = min(v, (v - m) & 0xFFFF)
+            assert v == w % m, (m, w)
 
 
 def _exact_rn(X, sc):
