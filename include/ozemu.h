@@ -8,8 +8,8 @@
  * "convert"); A' and B' are reduced modulo pairwise-coprime moduli (Sec.
  * II-B); each modulus's product runs as an exact INT8 GEMM with INT32
  * accumulation (Sec. IV-C); the epilogue reduces each product modulo its
- * modulus (Sec. V-C); Reconstruct applies the CRT, rounds once and unscales
- * (Sec. V-A, V-C). The result is C = RN(A'B' * 2^-(s_i + t_j)) entry by
+ * modulus (Sec. V-D); Reconstruct applies the CRT, rounds once and unscales
+ * (Sec. V-A, V-D). The result is C = RN(A'B' * 2^-(s_i + t_j)) entry by
  * entry, one rounding, whenever the CRT window (eq. "ov-crtgen") and the
  * accumulator bound (eq. "ov-accgen") hold; the library checks both before
  * any launch.
@@ -151,6 +151,25 @@ ozemu_status ozemu_workspace_size(ozemu_plan plan, int64_t m, int64_t n, int64_t
 ozemu_status ozemu_dgemm(ozemu_plan plan, void* stream, int64_t m, int64_t n, int64_t k,
                          const double* A, int64_t lda, const double* B, int64_t ldb,
                          double* C, int64_t ldc, void* workspace, size_t ws_bytes);
+
+/* Blocked call (Sec. V-B, "Slabs"): C = A B with the inner dimension cut
+ * into slabs of k_slab terms (the last may be shorter). Each slab's residue
+ * GEMMs accumulate on their own, so only k_slab is held to the INT32
+ * accumulation cap (ozemu_plan_k_max); k itself may exceed it, up to the
+ * reconstruction cap of the modulus set (the kept bits are those of the
+ * whole k, as in ozemu_dgemm). Each slab's residues are added into a running
+ * residue mod m_l, so the result is bitwise that of the unblocked definition;
+ * the planes of one slab exist at a time, so k may also be longer than
+ * the planes of a whole call could hold. INT8 plans in modes F53 and W
+ * (OZEMU_ERR_UNSUPPORTED otherwise); k_slab > cap: OZEMU_ERR_K_TOO_LARGE.
+ * Pointers, strides, stream and workspace rules as for ozemu_dgemm, with
+ * ozemu_blocked_workspace_size bytes of workspace. */
+ozemu_status ozemu_blocked_workspace_size(ozemu_plan plan, int64_t m, int64_t n, int64_t k,
+                                          int64_t k_slab, size_t* bytes);
+ozemu_status ozemu_dgemm_blocked(ozemu_plan plan, void* stream, int64_t m, int64_t n, int64_t k,
+                                 int64_t k_slab, const double* A, int64_t lda, const double* B,
+                                 int64_t ldb, double* C, int64_t ldc, void* workspace,
+                                 size_t ws_bytes);
 
 /* ---- The five phases as separate calls (Sec. V-A), for callers that keep
  * intermediates (autograd, verification). Shapes and strides as in

@@ -24,12 +24,12 @@ Steps (Sec. II-A eq. "convert", Sec. II-B, Sec. III-C, Sec. V-A)
 3. Truncation: A' = trunc(a * 2**s_i) with s_i = beta_A - e_i (eq.
    "convert"); |A'| < 2**beta_A.
 4. Balanced residues modulo m, nearest zero, ties to -m/2 so that m = 256
-   fits INT8 (Sec. II-B; Sec. V-C stores them in two's complement).
+   fits INT8 (Sec. II-B; Sec. V-D stores them in two's complement).
 5. Residue GEMM W = R_A R_B exact (|W| <= K r_A r_B <= 2**31 - 1), and
    Z = W mod m in [0, m) (Sec. III-A: sum_k lambda_k W_k == A'B' mod m).
 6. CRT: X == Z_l mod m_l, X in [0, P), balanced to X - P when X > (P-1)/2
    (Sec. II-B; the window is strict so the tie is unreachable).
-7. One rounding: C_ij = RN(X_ij * 2**-(s_i + t_j)) (Sec. II-A, Sec. V-C).
+7. One rounding: C_ij = RN(X_ij * 2**-(s_i + t_j)) (Sec. II-A, Sec. V-D).
 
 Non-finite input (the paper is silent): every entry of C in a row of A or
 column of B holding a NaN or an infinity is NaN; those rows and columns

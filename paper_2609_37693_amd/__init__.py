@@ -15,7 +15,7 @@ import ctypes as C
 from . import _lib
 from ._lib import OzemuError, SCALING, SHIFT_NONFINITE
 
-__all__ = ["Plan", "dgemm", "scale", "reduce", "residue_gemm", "reconstruct", "OzemuError",
+__all__ = ["Plan", "dgemm", "dgemm_blocked", "blocked_workspace_size", "scale", "reduce", "residue_gemm", "reconstruct", "OzemuError",
            "SHIFT_NONFINITE", "version", "ForwardCache", "dgemm_fwd_cache", "dgemm_bwd", "Group",
            "dgemm_grouped"]
 
@@ -168,6 +168,35 @@ def dgemm(A, B, plan: Plan, out=None, workspace=None):
     _lib.check(plan._lib.ozemu_dgemm(plan.handle, _stream_ptr(), m, n, k, _ptr(A), lda, _ptr(B),
                                      ldb, _ptr(out), ldc, _ptr(workspace),
                                      workspace.numel() if workspace is not None else 0))
+    return out
+
+
+def blocked_workspace_size(plan: Plan, m: int, n: int, k: int, k_slab: int) -> int:
+    v = C.c_size_t()
+    _lib.check(plan._lib.ozemu_blocked_workspace_size(plan.handle, int(m), int(n), int(k),
+                                                      int(k_slab), C.byref(v)))
+    return v.value
+
+
+def dgemm_blocked(A, B, plan: Plan, k_slab: int, out=None, workspace=None):
+    """C = A @ B with the inner dimension in slabs of k_slab terms (the
+    blocked call): k may exceed the plan's accumulation cap."""
+    torch = _torch()
+    A, lda = _matrix(A, "A")
+    B, ldb = _matrix(B, "B")
+    m, k = A.shape
+    k2, n = B.shape
+    if k != k2:
+        raise ValueError("inner dimensions differ: %d vs %d" % (k, k2))
+    if out is None:
+        out = torch.empty((m, n), dtype=torch.float64, device=A.device)
+    ldc = out.stride(0) if out.numel() > 0 else max(1, n)
+    if workspace is None:
+        nbytes = blocked_workspace_size(plan, m, n, k, k_slab)
+        workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=A.device)
+    _lib.check(plan._lib.ozemu_dgemm_blocked(plan.handle, _stream_ptr(), m, n, k, int(k_slab),
+                                             _ptr(A), lda, _ptr(B), ldb, _ptr(out), ldc,
+                                             _ptr(workspace), workspace.numel()))
     return out
 
 

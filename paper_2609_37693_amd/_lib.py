@@ -44,6 +44,10 @@ SIGNATURES = {
     "ozemu_workspace_size": (_st, [_vp, _i64, _i64, _i64, C.POINTER(C.c_size_t)]),
     "ozemu_dgemm": (_st, [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
                           C.c_size_t]),
+    "ozemu_blocked_workspace_size": (_st, [_vp, _i64, _i64, _i64, _i64,
+                                           C.POINTER(C.c_size_t)]),
+    "ozemu_dgemm_blocked": (_st, [_vp, _vp, _i64, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp,
+                                  _i64, _vp, C.c_size_t]),
     "ozemu_scale": (_st, [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp,
                           C.c_size_t]),
     "ozemu_reduce": (_st, [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp,

@@ -13,6 +13,7 @@
 #include "../../include/ozemu.h"
 #include "ozemu_internal.hpp"
 #include "plan.hpp"
+#include "slabs.hpp"
 
 struct ozemu_plan_s {
     ozemu::Plan p;
@@ -653,6 +654,129 @@ ozemu_status ozemu_dgemm(ozemu_plan plan, void* stream, int64_t m, int64_t n, in
         return s;
     return hip_check(ozemu::launch_reconstruct(st, p.crt, m, n, d.m_pad, d.n_pad, z, sa, sb, C, ldc),
                      "reconstruct");
+}
+
+namespace {
+
+// Workspace of the blocked call: shifts, the planes of one slab, the running
+// residues and (with more than one slab) one slab's residues.
+struct BlockedLayout {
+    size_t shift_a, shift_b, planes_a, planes_b, z_run, z_slab, total;
+};
+
+BlockedLayout blocked_layout(const ozemu::Plan& p, int64_t m, int64_t n, int64_t k,
+                             int64_t k_slab) {
+    const Dims d = dims_of(m, n, std::min(k, k_slab));
+    BlockedLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    const size_t N = (size_t)p.n;
+    L.shift_a = take(sizeof(int32_t) * (size_t)std::max<int64_t>(m, 1));
+    L.shift_b = take(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
+    L.planes_a = take(N * (size_t)d.m_pad * (size_t)d.k_pad);
+    L.planes_b = take(N * (size_t)d.n_pad * (size_t)d.k_pad);
+    L.z_run = take(N * (size_t)d.m_pad * (size_t)d.n_pad);
+    L.z_slab = k > k_slab ? take(N * (size_t)d.m_pad * (size_t)d.n_pad) : L.z_run;
+    L.total = off;
+    return L;
+}
+
+// The accumulation cap applies to a slab, the reconstruction cap to the
+// whole inner dimension.
+ozemu_status check_blocked(const ozemu::Plan& p, int64_t m, int64_t n, int64_t k,
+                           int64_t k_slab) {
+    if (is_fp(p))
+        return fail(OZEMU_ERR_UNSUPPORTED,
+                    "blocked call: INT8 plans only (float-channel plans take their slab "
+                    "length at creation)");
+    if (p.scaling == OZEMU_SCALE_BOUND)
+        return fail(OZEMU_ERR_UNSUPPORTED, "blocked call: scaling modes F53 and W only");
+    if (m < 0 || n < 0 || k < 0) return fail(OZEMU_ERR_INVALID_ARG, "negative dimension");
+    if (m > (1ll << 31) || n > (1ll << 31)) return fail(OZEMU_ERR_INVALID_ARG, "dimension too large");
+    if (k_slab < 1) return fail(OZEMU_ERR_INVALID_ARG, "k_slab must be positive");
+    if (k_slab > p.kappa_acc)
+        return fail(OZEMU_ERR_K_TOO_LARGE,
+                    "k_slab = " + std::to_string(k_slab) + " exceeds the INT32 accumulation cap " +
+                        std::to_string(p.kappa_acc) + " of this modulus set");
+    if (p.scaling == OZEMU_SCALE_F53 && k > 0 && !ozemu::window_holds(p, k, 53, 53))
+        return fail(OZEMU_ERR_K_TOO_LARGE,
+                    "k = " + std::to_string(k) +
+                        " exceeds the reconstruction cap of this modulus set at 53 bits");
+    if (p.scaling == OZEMU_SCALE_WINDOW && k > 0 && ozemu::window_bits(p, k) < 2)
+        return fail(OZEMU_ERR_K_TOO_LARGE, "modulus product too small for this k");
+    return ok();
+}
+
+}  // namespace
+
+ozemu_status ozemu_blocked_workspace_size(ozemu_plan plan, int64_t m, int64_t n, int64_t k,
+                                          int64_t k_slab, size_t* bytes) {
+    if (ozemu_status s = check_plan(plan)) return s;
+    if (!bytes) return fail(OZEMU_ERR_INVALID_ARG, "NULL output");
+    if (ozemu_status s = check_blocked(plan->p, m, n, k, k_slab)) return s;
+    *bytes = blocked_layout(plan->p, m, n, k, k_slab).total;
+    return ok();
+}
+
+ozemu_status ozemu_dgemm_blocked(ozemu_plan plan, void* stream, int64_t m, int64_t n, int64_t k,
+                                 int64_t k_slab, const double* A, int64_t lda, const double* B,
+                                 int64_t ldb, double* C, int64_t ldc, void* workspace,
+                                 size_t ws_bytes) {
+    if (ozemu_status s = check_plan(plan)) return s;
+    const ozemu::Plan& p = plan->p;
+    if (ozemu_status s = check_blocked(p, m, n, k, k_slab)) return s;
+    if (m == 0 || n == 0) return ok();
+    if (ozemu_status s = check_operands(m, n, k, A, lda, B, ldb)) return s;
+    if (!C || ldc < n) return fail(OZEMU_ERR_INVALID_ARG, "C is NULL or ldc < n");
+    hipStream_t st = (hipStream_t)stream;
+    if (k == 0) return hip_check(ozemu::launch_zero_c(st, m, n, C, ldc), "zero C");
+    const BlockedLayout L = blocked_layout(p, m, n, k, k_slab);
+    if (!workspace || ws_bytes < L.total)
+        return fail(OZEMU_ERR_WORKSPACE, "workspace smaller than ozemu_blocked_workspace_size");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255)
+        return fail(OZEMU_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+    char* ws = static_cast<char*>(workspace);
+    int32_t* sa = reinterpret_cast<int32_t*>(ws + L.shift_a);
+    int32_t* sb = reinterpret_cast<int32_t*>(ws + L.shift_b);
+    int8_t* pa = reinterpret_cast<int8_t*>(ws + L.planes_a);
+    int8_t* pb = reinterpret_cast<int8_t*>(ws + L.planes_b);
+    uint8_t* z_run = reinterpret_cast<uint8_t*>(ws + L.z_run);
+    uint8_t* z_slab = reinterpret_cast<uint8_t*>(ws + L.z_slab);
+    // shifts and kept bits from the whole inner dimension
+    if (ozemu_status s = run_scale(p, st, m, n, k, A, lda, B, ldb, sa, sb, nullptr)) return s;
+    const bool big = big_encode(p, k);
+    Dims d{};
+    for (int64_t h0 = 0; h0 < k; h0 += k_slab) {
+        const int64_t kt = std::min(k_slab, k - h0);
+        d = dims_of(m, n, kt);
+        uint8_t* out = h0 == 0 ? z_run : z_slab;
+        if (ozemu_status s = hip_check(
+                ozemu::launch_encode_a(st, p.mod, m, kt, A + h0, lda, sa, d.m_pad, d.k_pad, pa, big),
+                "encode_a"))
+            return s;
+        if (ozemu_status s = hip_check(
+                ozemu::launch_encode_b(st, p.mod, kt, n, B + h0 * ldb, ldb, sb, d.n_pad, d.k_pad,
+                                       pb, big),
+                "encode_b"))
+            return s;
+        if (ozemu_status s = hip_check(
+                ozemu::launch_residue_gemm(st, p.mod, d.m_pad, d.n_pad, d.k_pad, pa, pb, out),
+                "residue_gemm"))
+            return s;
+        if (h0 > 0)
+            if (ozemu_status s = hip_check(ozemu::launch_add_residues(st, p.mod, p.n,
+                                                                      d.m_pad * d.n_pad, z_run,
+                                                                      z_slab),
+                                           "add_residues"))
+                return s;
+    }
+    return hip_check(
+        ozemu::launch_reconstruct(st, p.crt, m, n, d.m_pad, d.n_pad, z_run, sa, sb, C, ldc),
+        "reconstruct");
 }
 
 namespace {

@@ -1,4 +1,4 @@
-// Reconstruct (Sec. V-A phase 5, Sec. V-C "Reconstruct"): for each output
+// Reconstruct (Sec. V-A phase 5, Sec. V-D "Reconstruct"): for each output
 // entry, the balanced CRT solution X of its residues, then one rounding of
 // X 2^-(s_i + t_j) into FP64.
 //

@@ -1,4 +1,4 @@
-// Reduce phase (Sec. V-A phase 2, Sec. V-C "Reduce"): applies Scale's shifts,
+// Reduce phase (Sec. V-A phase 2, Sec. V-D "Reduce"): applies Scale's shifts,
 // truncates each entry (eq. "convert") without storing A' or B', and writes
 // its balanced residue modulo every modulus of the plan as int8 (two's
 // complement) into the residue planes. Each FP64 entry is read once; all

@@ -231,3 +231,37 @@ def test_group_host_side():
     assert st == S.OZEMU_ERR_UNSUPPORTED
     assert _group_create(4097, [w] * 4097, [1] * 4097, [1] * 4097, [1] * 4097)[0] == \
         S.OZEMU_ERR_INVALID_ARG
+
+
+def test_blocked_call_host_side():
+    """Blocked call: the accumulation cap binds the slab, the reconstruction
+    cap the whole k; other plans are refused; errors come before any launch."""
+    S = _lib
+    lib = _lib.load()
+    plan = oz.Plan(num_moduli=16, scaling="W")
+    cap = plan.k_max()
+    # k beyond the cap is accepted with a slab within it
+    one = oz.blocked_workspace_size(plan, 4, 5, 64, 64)
+    two = oz.blocked_workspace_size(plan, 4, 5, 128, 64)
+    assert two > one  # the second slab needs its own residues
+    assert oz.blocked_workspace_size(plan, 4, 5, cap + 10, cap) > 0
+    for args, want in [((4, 5, 100, cap + 1), S.OZEMU_ERR_K_TOO_LARGE),
+                       ((4, 5, 100, 0), S.OZEMU_ERR_INVALID_ARG),
+                       ((-1, 5, 100, 10), S.OZEMU_ERR_INVALID_ARG)]:
+        v = C.c_size_t()
+        assert lib.ozemu_blocked_workspace_size(plan.handle, *args, C.byref(v)) == want
+    f53 = oz.Plan(num_moduli=14, scaling="F53")  # reconstruction cap at 53 bits: k = 10
+    v = C.c_size_t()
+    assert lib.ozemu_blocked_workspace_size(f53.handle, 4, 4, 11, 4, C.byref(v)) == \
+        S.OZEMU_ERR_K_TOO_LARGE
+    for other in (oz.Plan(num_moduli=16, scaling="G"), oz.Plan(format="E4M3", scaling="W")):
+        assert lib.ozemu_blocked_workspace_size(other.handle, 4, 4, 64, 32, C.byref(v)) == \
+            S.OZEMU_ERR_UNSUPPORTED
+    # no workspace, NULL operands; empty output is a no-op
+    call = lambda m, n, k, ks, A=8, ws=0, nb=0: lib.ozemu_dgemm_blocked(
+        plan.handle, None, m, n, k, ks, C.c_void_p(A), max(k, 1), C.c_void_p(8), max(n, 1),
+        C.c_void_p(8), max(n, 1), C.c_void_p(ws), nb)
+    assert call(4, 5, 100, 50) == S.OZEMU_ERR_WORKSPACE
+    assert call(4, 5, 100, 50, A=0) == S.OZEMU_ERR_INVALID_ARG
+    assert call(4, 5, 100, cap + 1) == S.OZEMU_ERR_K_TOO_LARGE
+    assert call(0, 5, 100, 50) == S.OZEMU_OK

@@ -48,7 +48,7 @@ def test_more_than_one_gpu_is_refused():
 def test_certified_bound_covers_exact_errors(phi, shape, nm, seed, cap):
     """bench.py's whole-matrix bound is an upper bound of the exact scaled
     error on every entry of the oracle's product, with the oracle's shifts,
-    and stays within the entrywise bound of Sec. V-D's error analysis (it
+    and stays within the entrywise bound of Sec. VIII-E's error analysis (it
     is not vacuous)."""
     torch = pytest.importorskip("torch")
     from oracle import moduli, scheme
