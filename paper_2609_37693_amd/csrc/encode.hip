@@ -148,6 +148,77 @@ __device__ __forceinline__ uint4 residues16(const Entry8* ent, const ModConsts& 
                       pack4(r[8], r[9], r[10], r[11]), pack4(r[12], r[13], r[14], r[15]));
 }
 
+// The exact form's entries when every |A'| of a wave is below 2^94
+// (positive shift at most kMidShift): A' as twelve signed base-256 digits
+// (the bytes of A' + 0x80...80 over 96 bits, top bits flipped), written over
+// the entry's own registers (lo, hi, negm = digit words 0, 1, 2), and per
+// modulus three signed byte dot products with the balanced weights
+// 2^(8 i) mod m (bytes 8..11 from MidConsts) on top of 2 km, a multiple of m
+// in [2^18, 2^18 + 2m): |sum| <= 12 128 128 < 2^18 keeps t in [0, 2^19).
+// No shift table and no per-modulus multiply.
+constexpr int kMidShift = 41;  // |A'| = mant 2^sh < 2^53 2^41
+
+struct MidConsts {
+    int32_t s8c[kMaxModuli];  // balanced 2^(64 + 8 i) mod m_l, i = 0..3, as signed bytes
+    int on;                   // 0: the exact form only
+};
+
+__device__ __forceinline__ bool mid_fits(const Entry8& e) { return e.sh <= kMidShift; }
+
+__device__ __forceinline__ void to_mid(Entry8& e) {
+    const bool neg = e.negm != 0u;
+    const uint64_t w = ((uint64_t)e.hi << 32) | e.lo;
+    const uint64_t v = neg ? (uint64_t)0 - w : w;  // |A'| 2^-sh, below 2^53
+    const int sh = e.sh;                           // 0 .. kMidShift
+    const uint64_t lo = v << sh;
+    const uint32_t hi = sh > 0 ? (uint32_t)(v >> (64 - sh)) : 0u;
+    const uint64_t nlo = neg ? (uint64_t)0 - lo : lo;  // two's complement over 96 bits
+    const uint32_t nhi = neg ? ~hi + (lo == 0 ? 1u : 0u) : hi;
+    const uint64_t y0 = nlo + 0x8080808080808080ull;
+    const uint32_t y1 = nhi + 0x80808080u + (y0 < nlo ? 1u : 0u);
+    e.lo = (uint32_t)y0 ^ 0x80808080u;
+    e.hi = (uint32_t)(y0 >> 32) ^ 0x80808080u;
+    e.negm = y1 ^ 0x80808080u;
+    e.sh = 0;
+}
+
+__device__ __forceinline__ int32_t mid_residue(const Entry8& e, const ModConsts& mc,
+                                               const MidConsts& md, int l) {
+    int32_t w0, w1, w2, u;
+    asm("v_mov_b32 %0, %1" : "=v"(w0) : "s"(mc.s8[l][0]));
+    asm("v_mov_b32 %0, %1" : "=v"(w1) : "s"(mc.s8[l][1]));
+    asm("v_mov_b32 %0, %1" : "=v"(w2) : "s"(md.s8c[l]));
+    asm("v_dot4_i32_i8 %0, %1, %2, %3" : "=v"(u) : "v"(e.lo), "v"(w0), "s"(2u * mc.km[l]));
+    u = __builtin_amdgcn_sdot4((int32_t)e.hi, w1, u, false);
+    u = __builtin_amdgcn_sdot4((int32_t)e.negm, w2, u, false);
+    return balanced19((uint32_t)u, mc.m[l], mc.rcp_up[l]);
+}
+
+__device__ __forceinline__ uint4 mid_residues16(const Entry8* ent, const ModConsts& mc,
+                                                const MidConsts& md, int l) {
+    int32_t r[kEncVec];
+#pragma unroll
+    for (int q = 0; q < kEncVec; ++q) r[q] = mid_residue(ent[q], mc, md, l);
+    return make_uint4(pack4(r[0], r[1], r[2], r[3]), pack4(r[4], r[5], r[6], r[7]),
+                      pack4(r[8], r[9], r[10], r[11]), pack4(r[12], r[13], r[14], r[15]));
+}
+
+// True in every thread of the workgroup when every entry of the workgroup
+// fits the 96-bit form (kBig kernels given the constants). A block-wide
+// vote: every thread of the workgroup must call it.
+template <bool kBig>
+__device__ __forceinline__ bool block_mid(const Entry8* ent, const MidConsts* md) {
+    if constexpr (!kBig) {
+        return false;
+    } else {
+        if (md == nullptr || !md->on) return false;
+        bool fits = true;
+#pragma unroll
+        for (int q = 0; q < kEncVec; ++q) fits = fits && mid_fits(ent[q]);
+        return __syncthreads_and(fits) != 0;
+    }
+}
+
 // Shift of an entry whose row (or column) shift is s and whose inner index
 // carries the fold f: s - f, the marker if either is the marker.
 template <bool kFold>
@@ -190,39 +261,58 @@ __device__ __forceinline__ void encode_a_body(const ModConsts& mc, int64_t m, in
                                               const double* A, int64_t lda,
                                               const int32_t* shift_a, const int32_t* fold,
                                               int64_t m_pad, int64_t k_pad, int8_t* planes,
-                                              int64_t c, uint8_t* p2) {
-    fill_p2<kBig>(mc, p2);
+                                              int64_t c, uint8_t* p2,
+                                              const MidConsts* md = nullptr) {
     const int64_t tiles_k = k_pad / kPlaneK;
     const int64_t tile = c >> 8;
     const int t = (int)(c & 255);
     const int64_t i = (tile / tiles_k) * 64 + (t >> 2);
     const int64_t h = (tile % tiles_k) * kPlaneK + (t & 3) * kEncVec;
+    const bool live = i < m && h < k;
+    Entry8 ent[kEncVec];
+    if (live) {
+        const int32_t s = shift_a[i];
+        const double* row = A + i * lda;
+        if (h + kEncVec <= k && ((reinterpret_cast<uintptr_t>(row + h) & 15) == 0)) {
+            const double2* p2v = reinterpret_cast<const double2*>(row + h);
+#pragma unroll
+            for (int q = 0; q < kEncVec / 2; ++q) {
+                double2 v = p2v[q];
+                ent[2 * q] = make_entry8<kBig>(v.x, entry_shift<kFold>(s, fold, h + 2 * q));
+                ent[2 * q + 1] =
+                    make_entry8<kBig>(v.y, entry_shift<kFold>(s, fold, h + 2 * q + 1));
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < kEncVec; ++q) {
+                const bool in = h + q < k;
+                double v = in ? row[h + q] : 0.0;
+                ent[q] = make_entry8<kBig>(v, in ? entry_shift<kFold>(s, fold, h + q) : 0);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < kEncVec; ++q) ent[q] = Entry8{0u, 0u, 0u, 0};
+    }
+    // every thread votes before any leaves: the 96-bit form for the whole
+    // workgroup, else the shift table
+    const bool use_mid = block_mid<kBig>(ent, md);
+    if (!use_mid) fill_p2<kBig>(mc, p2);
     if (i >= m_pad) return;
     const int64_t plane_stride = m_pad * k_pad;
     int8_t* out = planes + plane_offset(i, h, k_pad);
-    if (i >= m || h >= k) {
+    if (!live) {
         for (int l = 0; l < mc.n; ++l)
             *reinterpret_cast<uint4*>(out + (int64_t)l * plane_stride) = make_uint4(0, 0, 0, 0);
         return;
     }
-    Entry8 ent[kEncVec];
-    const int32_t s = shift_a[i];
-    const double* row = A + i * lda;
-    if (h + kEncVec <= k && ((reinterpret_cast<uintptr_t>(row + h) & 15) == 0)) {
-        const double2* p2v = reinterpret_cast<const double2*>(row + h);
+    if (use_mid) {
 #pragma unroll
-        for (int q = 0; q < kEncVec / 2; ++q) {
-            double2 v = p2v[q];
-            ent[2 * q] = make_entry8<kBig>(v.x, entry_shift<kFold>(s, fold, h + 2 * q));
-            ent[2 * q + 1] = make_entry8<kBig>(v.y, entry_shift<kFold>(s, fold, h + 2 * q + 1));
-        }
-    } else {
-#pragma unroll
-        for (int q = 0; q < kEncVec; ++q) {
-            const bool in = h + q < k;
-            double v = in ? row[h + q] : 0.0;
-            ent[q] = make_entry8<kBig>(v, in ? entry_shift<kFold>(s, fold, h + q) : 0);
-        }
+        for (int q = 0; q < kEncVec; ++q) to_mid(ent[q]);
+        for (int l = 0; l < mc.n; ++l)
+            *reinterpret_cast<uint4*>(out + (int64_t)l * plane_stride) =
+                mid_residues16(ent, mc, *md, l);
+        return;
     }
     for (int l = 0; l < mc.n; ++l)
         *reinterpret_cast<uint4*>(out + (int64_t)l * plane_stride) =
@@ -236,10 +326,10 @@ __global__ __launch_bounds__(kEncThreads) void encode_a_kernel(ModConsts mc, int
                                                                const int32_t* shift_a,
                                                                const int32_t* fold,
                                                                int64_t m_pad, int64_t k_pad,
-                                                               int8_t* planes) {
+                                                               int8_t* planes, MidConsts md) {
     __shared__ uint8_t p2[kBig ? kMaxModuli * kMaxShift : 1];
     encode_a_body<kBig, kFold>(mc, m, k, A, lda, shift_a, fold, m_pad, k_pad, planes,
-                               (int64_t)blockIdx.x * kChunksPerBlock + threadIdx.x, p2);
+                               (int64_t)blockIdx.x * kChunksPerBlock + threadIdx.x, p2, &md);
 }
 
 // Workgroup (bx, by) of encode_b: a 64 (k) x 64 (n) tile of B. Thread t
@@ -255,7 +345,8 @@ __device__ __forceinline__ void encode_b_body(const ModConsts& mc, int64_t k, in
                                               const double* B, int64_t ldb,
                                               const int32_t* shift_b, const int32_t* fold,
                                               int64_t n_pad, int64_t k_pad, int8_t* planes,
-                                              int64_t bx, int64_t by, int8_t* tile, uint8_t* p2) {
+                                              int64_t bx, int64_t by, int8_t* tile, uint8_t* p2,
+                                              const MidConsts* md = nullptr) {
     const int64_t j0 = bx * kTB;
     const int64_t h0 = by * kTB;
     const int64_t plane_stride = n_pad * k_pad;
@@ -268,7 +359,6 @@ __device__ __forceinline__ void encode_b_body(const ModConsts& mc, int64_t k, in
                 make_uint4(0, 0, 0, 0);
         return;
     }
-    fill_p2<kBig>(mc, p2);
     const int tj = threadIdx.x & 63;
     const int hq = threadIdx.x >> 6;  // 0..3
     const int64_t j = j0 + tj;
@@ -281,8 +371,15 @@ __device__ __forceinline__ void encode_b_body(const ModConsts& mc, int64_t k, in
         double v = in ? B[h * ldb + j] : 0.0;
         ent[q] = make_entry8<kBig>(v, in ? entry_shift<kFold>(s, fold, h) : 0);
     }
+    const bool use_mid = block_mid<kBig>(ent, md);  // uniform in the workgroup
+    if (!use_mid) fill_p2<kBig>(mc, p2);
+    if (use_mid) {
+#pragma unroll
+        for (int q = 0; q < kEncVec; ++q) to_mid(ent[q]);
+    }
     for (int l = 0; l < mc.n; ++l) {
-        const uint4 w = residues16<kBig>(ent, mc, l, p2 + l * kMaxShift);
+        const uint4 w = use_mid ? mid_residues16(ent, mc, *md, l)
+                                : residues16<kBig>(ent, mc, l, p2 + l * kMaxShift);
         if (l > 0) __syncthreads();  // previous modulus fully copied out
         *reinterpret_cast<uint4*>(tile + tj * kLdsRow + hq * kEncVec) = w;
         __syncthreads();
@@ -299,11 +396,11 @@ __global__ __launch_bounds__(kEncThreads) void encode_b_kernel(ModConsts mc, int
                                                                const int32_t* shift_b,
                                                                const int32_t* fold,
                                                                int64_t n_pad, int64_t k_pad,
-                                                               int8_t* planes) {
+                                                               int8_t* planes, MidConsts md) {
     __shared__ __align__(16) int8_t tile[kTB * kLdsRow];
     __shared__ uint8_t p2[kBig ? kMaxModuli * kMaxShift : 1];
     encode_b_body<kBig, kFold>(mc, k, n, B, ldb, shift_b, fold, n_pad, k_pad, planes, blockIdx.x,
-                               blockIdx.y, tile, p2);
+                               blockIdx.y, tile, p2, &md);
 }
 
 // ---- Reduce for float-alphabet channels ----
@@ -554,14 +651,38 @@ hipError_t launch_encode_fp(hipStream_t st, const FpConsts& fc, const uint8_t* t
     return hipGetLastError();
 }
 
+namespace {
+
+// Host: the weights of bytes 8..11 for the 96-bit form of the exact form.
+MidConsts mid_consts(const ModConsts& mc, bool big) {
+    MidConsts md{};
+    md.on = big ? 1 : 0;
+    for (int l = 0; l < mc.n && l < kMaxModuli; ++l) {
+        const uint32_t m = mc.m[l];
+        uint32_t w = 1 % m;
+        for (int b = 0; b < 64; ++b) w = (w * 2u) % m;  // 2^64 mod m
+        uint32_t packed = 0;
+        for (int i = 0; i < 4; ++i) {
+            const int32_t v = w >= (m + 1) / 2 ? (int32_t)w - (int32_t)m : (int32_t)w;
+            packed |= (uint32_t)(uint8_t)(int8_t)v << (8 * i);
+            w = (w * 256u) % m;
+        }
+        md.s8c[l] = (int32_t)packed;
+    }
+    return md;
+}
+
+}  // namespace
+
 hipError_t launch_encode_a(hipStream_t st, const ModConsts& mc, int64_t m, int64_t k,
                            const double* A, int64_t lda, const int32_t* shift_a, int64_t m_pad,
                            int64_t k_pad, int8_t* planes_a, bool big, const int32_t* fold) {
     if (m_pad <= 0 || k_pad <= 0) return hipSuccess;
     dim3 grid((unsigned)((m_pad * (k_pad / kEncVec) + kChunksPerBlock - 1) / kChunksPerBlock));
+    const MidConsts md = mid_consts(mc, big);
     auto go = [&](auto kernel) {
         kernel<<<grid, dim3(kEncThreads), 0, st>>>(mc, m, k, A, lda, shift_a, fold, m_pad, k_pad,
-                                                   planes_a);
+                                                   planes_a, md);
     };
     if (big)
         fold ? go(encode_a_kernel<true, true>) : go(encode_a_kernel<true, false>);
@@ -575,9 +696,10 @@ hipError_t launch_encode_b(hipStream_t st, const ModConsts& mc, int64_t k, int64
                            int64_t k_pad, int8_t* planes_b, bool big, const int32_t* fold) {
     if (n_pad <= 0 || k_pad <= 0) return hipSuccess;
     dim3 grid((unsigned)(n_pad / kTB), (unsigned)(k_pad / kTB));
+    const MidConsts md = mid_consts(mc, big);
     auto go = [&](auto kernel) {
         kernel<<<grid, dim3(kEncThreads), 0, st>>>(mc, k, n, B, ldb, shift_b, fold, n_pad, k_pad,
-                                                   planes_b);
+                                                   planes_b, md);
     };
     if (big)
         fold ? go(encode_b_kernel<true, true>) : go(encode_b_kernel<true, false>);

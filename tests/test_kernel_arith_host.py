@@ -136,3 +136,47 @@ def test_reconstruct_fast_rounding_is_correct_rounding(CB, KC, bits):
             taken += 1
             assert got == _exact_rn(X, sc), (X, sc)
     assert taken > 10000
+
+
+def _to_mid(v, sh, neg):
+    """The exact-form kernels' 96-bit signed digits of A' = +-v 2^sh:
+    (A' + 0x80...80 mod 2^96) with each byte's top bit flipped."""
+    M64, M32 = (1 << 64) - 1, (1 << 32) - 1
+    lo = (v << sh) & M64
+    hi = (v >> (64 - sh)) & M32 if sh > 0 else 0
+    nlo = (-lo) & M64 if neg else lo
+    nhi = ((~hi) + (1 if lo == 0 else 0)) & M32 if neg else hi
+    y0 = (nlo + 0x8080808080808080) & M64
+    y1 = (nhi + 0x80808080 + (1 if y0 < nlo else 0)) & M32
+    words = [(y0 & M32) ^ 0x80808080, (y0 >> 32) ^ 0x80808080, y1 ^ 0x80808080]
+    return [((w >> (8 * i)) & 0xFF) - 256 * (((w >> (8 * i)) & 0xFF) >= 128)
+            for w in words for i in range(4)]
+
+
+def test_reduce_96_bit_signed_digits_and_residue():
+    """Twelve signed digits rebuild +-v 2^sh exactly for |A'| < 2^94, and
+    three signed dot products on top of 2 km stay in [0, 2^19) and give the
+    balanced residue through the magic-constant FMA, for every m <= 256."""
+    rnd = random.Random(9)
+    cases = [(1, 0, False), (1, 0, True), ((1 << 53) - 1, 41, False), ((1 << 53) - 1, 41, True),
+             (1 << 52, 12, True), ((1 << 53) - 1, 11, True), (12345, 0, True)]
+    cases += [(rnd.getrandbits(rnd.randint(1, 53)), rnd.randint(0, 41), rnd.random() < 0.5)
+              for _ in range(300)]
+    for m in range(2, 257):
+        km = m * -(-(1 << 17) // m)
+        wts = []
+        for j in range(12):
+            w = pow(2, 8 * j, m)
+            wts.append(w - m if w >= (m + 1) // 2 else w)
+        M, E = _f32_parts(_rcp_up(m))
+        for v, sh, neg in cases:
+            a = (-1 if neg else 1) * (v << sh)
+            d = _to_mid(v, sh, neg)
+            assert all(-128 <= x <= 127 for x in d)
+            assert sum(x << (8 * i) for i, x in enumerate(d)) == a
+            t = 2 * km + sum(x * w for x, w in zip(d, wts))
+            assert 0 <= t < (1 << 19)
+            q = int(_rne_shift(np.array([t * M], dtype=np.int64), -E)[0])
+            r = (t + int(_mul24(np.array([(0x400000 + q) & 0xFFFFFF]), np.array([-m]))[0])) & 0xFF
+            want = a - m * ((2 * a + m) // (2 * m))  # balanced residue of A'
+            assert r == want & 0xFF, (m, v, sh, neg)
