@@ -373,3 +373,27 @@ def test_kept_bits_at_the_reduce_threshold(nmod, shape):
     C = host(oz.dgemm(dev(A), dev(B), plan))
     ref = scheme.emulate(A, B, plan.moduli(), "W", keep=False)["C"]
     assert np.array_equal(C, ref)
+
+
+@pytest.mark.parametrize("nmod", [24, 28, 32])
+@pytest.mark.parametrize("phi", [0.5, 4.0])
+def test_exact_form_of_reduce_both_paths(nmod, phi):
+    """Kept bits above 62 (89, 102 and 116 per side here): workgroups whose
+    entries all stay below 2^94 take the twelve-signed-digit form, the
+    others the shift-table form; with phi = 4 one call holds both. The
+    product is bitwise the oracle's."""
+    import torch
+    m, n, k = 200, 150, 300
+    A, B = operand_pair(m, n, k, phi, 7)
+    plan = oz.Plan(num_moduli=nmod, scaling="W")
+    print("exact form", nmod, phi, plan.kept_bits(k), flush=True)
+    C = host(oz.dgemm(dev(A), dev(B), plan))
+    torch.cuda.synchronize()
+    ref = scheme.emulate(A, B, plan.moduli(), "W", blas=True, keep=False)["C"]
+    assert np.array_equal(C, ref)
+    dA, dB = dev(A), dev(B)
+    sa, sb = oz.scale(dA, dB, plan)
+    pa, pb = oz.reduce(dA, dB, sa, sb, plan)
+    PA, PB = oracle_planes(A, B, plan.moduli(), "W", plan.plane_dims(m, n, k))
+    assert np.array_equal(from_blocked(host(pa)), PA)
+    assert np.array_equal(from_blocked(host(pb)), PB)
