@@ -7,6 +7,12 @@
 // Planes of A hold row i of A' K-contiguously and planes of B column j of B'
 // (a transpose, done through LDS), both in the blocked GEMM order of
 // plane_offset, so the GEMM reads each K step of a tile as one block.
+//
+// Three forms of an entry, by the plan's kept bits: at most 62, A' as eight
+// signed base-256 digits and two byte dot products per modulus; above 62
+// (the exact form), twelve signed digits and three dot products while every
+// entry of the workgroup is below 2^94, else the bytes of the significand
+// and a factor 2^s mod m from an LDS table.
 #include "ozemu_internal.hpp"
 
 namespace ozemu {
