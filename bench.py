@@ -48,12 +48,13 @@ def parse():
                     help="fp workload: comma-separated GEMM counts (0: least count for the "
                          "window at K = 16384)")
     ap.add_argument("--workload", default="dgemm",
-                    choices=["dgemm", "mlp", "grouped", "fp", "sweep"],
+                    choices=["dgemm", "mlp", "grouped", "fp", "sweep", "blocked"],
                     help="dgemm: the 8192^3 emulated DGEMM (default); mlp: one training "
                          "step of a 4-layer tanh MLP through the cached-residue backward; "
                          "grouped: 512 uneven products as one grouped run in a HIP graph; "
                          "sweep: the 8192^3 DGEMM over moduli counts and phi, time and "
-                         "exact scaled error on sampled entries")
+                         "exact scaled error on sampled entries; blocked: the blocked call "
+                         "at an inner dimension beyond the INT32 accumulation cap")
     ap.add_argument("--moduli-list", default="10,11,12,13,14,15,16,17,18,19,20",
                     help="sweep: moduli counts")
     ap.add_argument("--phi-list", default="0.5,4", help="sweep: phi values")
@@ -63,6 +64,10 @@ def parse():
     ap.add_argument("--group-moduli", type=int, default=None,
                     help="grouped: one moduli count for every problem (default: chosen per "
                          "problem for 55 kept bits)")
+    ap.add_argument("--blocked-mn", type=int, default=4096, help="blocked: m = n")
+    ap.add_argument("--blocked-k", type=int, default=262144, help="blocked: inner dimension")
+    ap.add_argument("--k-slab", type=int, default=0,
+                    help="blocked: slab length (0: the plan's accumulation cap)")
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--width", type=int, default=4096)
     return ap.parse_args()
@@ -503,6 +508,52 @@ def fp_main(args):
     print(json.dumps(out), flush=True)
 
 
+def blocked_main(args):
+    """The blocked call at m = n = 4096 and K = 262144 (twice the INT32
+    accumulation cap of 16 INT8 moduli), slabs at the cap, mode W; native
+    FP64 on the same operands; exact scaled error on sampled entries."""
+    import torch
+    import paper_2609_37693_amd as oz
+    from workloads import operand_pair
+    n, k = args.blocked_mn, args.blocked_k
+    A_h, B_h = operand_pair(n, n, k, args.phi, args.seed)
+    A = torch.from_numpy(A_h).cuda()
+    B = torch.from_numpy(B_h).cuda()
+    plan = oz.Plan(num_moduli=args.moduli, scaling=args.scaling)
+    k_slab = args.k_slab or plan.k_max()
+    C = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    ws = torch.empty(oz.blocked_workspace_size(plan, n, n, k, k_slab), dtype=torch.uint8,
+                     device="cuda")
+    run = lambda: oz.dgemm_blocked(A, B, plan, k_slab, out=C, workspace=ws)
+    ms = time_stream(run, args.steps, args.warmup)
+    run()
+    torch.cuda.synchronize()
+    ref = torch.empty_like(C)
+    native_ms = time_stream(lambda: torch.matmul(A, B, out=ref), max(3, args.steps // 2), 1)
+    rel = float(torch.linalg.norm(C - ref) / torch.linalg.norm(ref))
+    rng = np.random.default_rng(5)
+    rows = sorted(rng.choice(n, 2, replace=False).tolist())
+    cols = sorted(rng.choice(n, 2, replace=False).tolist())
+    err = exact_scaled_error(C.cpu().numpy(), A_h, B_h, rows, cols)
+    flops = 2.0 * n * n * k
+    out = {
+        "metric": "emulated DGEMM TFLOP/s, blocked call beyond the INT32 accumulation cap",
+        "value": flops / (ms * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": "blocked emulated DGEMM m = n = %d, k = %d in slabs of %d, "
+                               "phi = %g, %d moduli, mode %s" % (n, k, k_slab, args.phi,
+                                                                 args.moduli, args.scaling),
+                   "m": n, "n": n, "k": k, "k_slab": k_slab, "kept_bits": list(plan.kept_bits(k))},
+        "native_fp64": {"ms": native_ms, "value": flops / (native_ms * 1e-3) / 1e12},
+        "speedup_vs_native": native_ms / ms,
+        "rel_frobenius_vs_native": rel,
+        "scaled_error_sample": err,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -515,7 +566,7 @@ def main():
             print("no HIP device", file=sys.stderr)
             sys.exit(1)
         return {"mlp": mlp_main, "grouped": grouped_main, "fp": fp_main,
-                "sweep": sweep_main}[args.workload](args)
+                "sweep": sweep_main, "blocked": blocked_main}[args.workload](args)
     import paper_2609_37693_amd as oz
     from workloads import operand_pair
 

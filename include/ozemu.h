@@ -123,7 +123,9 @@ ozemu_status ozemu_plan_destroy(ozemu_plan plan);
 ozemu_status ozemu_plan_moduli(ozemu_plan plan, int32_t* out, int cap, int* count);
 
 /* Kept bits (beta_A, beta_B) the plan uses at inner dimension k in modes F53
- * and WINDOW (BOUND decides them per row and column on the device). */
+ * and WINDOW (BOUND decides them per row and column on the device). For
+ * INT8 plans k may exceed the accumulation cap (ozemu_plan_k_max), up to the
+ * reconstruction cap: such k runs in the blocked call. */
 ozemu_status ozemu_plan_kept_bits(ozemu_plan plan, int64_t k, int* beta_a, int* beta_b);
 
 /* Largest k the plan accepts: min(kappa_rec, kappa_acc) of eq. "caps"

@@ -155,6 +155,18 @@ ozemu_status check_shape(const ozemu::Plan& p, int64_t m, int64_t n, int64_t k) 
     return ok();
 }
 
+// The reconstruction caps of the whole inner dimension (INT8 plans, modes
+// F53 and W); the accumulation cap is checked separately.
+ozemu_status check_window(const ozemu::Plan& p, int64_t k) {
+    if (p.scaling == OZEMU_SCALE_F53 && k > 0 && !ozemu::window_holds(p, k, 53, 53))
+        return fail(OZEMU_ERR_K_TOO_LARGE,
+                    "k = " + std::to_string(k) +
+                        " exceeds the reconstruction cap of this modulus set at 53 bits");
+    if (p.scaling == OZEMU_SCALE_WINDOW && k > 0 && ozemu::window_bits(p, k) < 2)
+        return fail(OZEMU_ERR_K_TOO_LARGE, "modulus product too small for this k");
+    return ok();
+}
+
 ozemu_status check_operands(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda,
                             const void* B, int64_t ldb) {
     if (m > 0 && k > 0) {
@@ -404,7 +416,13 @@ ozemu_status ozemu_plan_kept_bits(ozemu_plan plan, int64_t k, int* beta_a, int* 
     if (!beta_a || !beta_b) return fail(OZEMU_ERR_INVALID_ARG, "NULL output");
     if (plan->p.scaling == OZEMU_SCALE_BOUND)
         return fail(OZEMU_ERR_UNSUPPORTED, "bound mode decides bits per row and column");
-    if (ozemu_status s = check_shape(plan->p, 1, 1, k)) return s;
+    if (is_fp(plan->p)) {
+        if (ozemu_status s = check_shape(plan->p, 1, 1, k)) return s;
+    } else {
+        // INT8: the window alone (k beyond the accumulation cap runs in the blocked call)
+        if (k < 0) return fail(OZEMU_ERR_INVALID_ARG, "negative dimension");
+        if (ozemu_status s = check_window(plan->p, k)) return s;
+    }
     kept_bits_of(plan->p, k, *beta_a, *beta_b);
     return ok();
 }
@@ -702,13 +720,7 @@ ozemu_status check_blocked(const ozemu::Plan& p, int64_t m, int64_t n, int64_t k
         return fail(OZEMU_ERR_K_TOO_LARGE,
                     "k_slab = " + std::to_string(k_slab) + " exceeds the INT32 accumulation cap " +
                         std::to_string(p.kappa_acc) + " of this modulus set");
-    if (p.scaling == OZEMU_SCALE_F53 && k > 0 && !ozemu::window_holds(p, k, 53, 53))
-        return fail(OZEMU_ERR_K_TOO_LARGE,
-                    "k = " + std::to_string(k) +
-                        " exceeds the reconstruction cap of this modulus set at 53 bits");
-    if (p.scaling == OZEMU_SCALE_WINDOW && k > 0 && ozemu::window_bits(p, k) < 2)
-        return fail(OZEMU_ERR_K_TOO_LARGE, "modulus product too small for this k");
-    return ok();
+    return check_window(p, k);
 }
 
 }  // namespace

@@ -245,6 +245,11 @@ def test_blocked_call_host_side():
     two = oz.blocked_workspace_size(plan, 4, 5, 128, 64)
     assert two > one  # the second slab needs its own residues
     assert oz.blocked_workspace_size(plan, 4, 5, cap + 10, cap) > 0
+    # the kept bits of such k follow the window over the whole k
+    P = 1
+    for mm in plan.moduli():
+        P *= mm
+    assert plan.kept_bits(2 * cap + 2) == scheme.kept_bits("W", P, 2 * cap + 2)
     for args, want in [((4, 5, 100, cap + 1), S.OZEMU_ERR_K_TOO_LARGE),
                        ((4, 5, 100, 0), S.OZEMU_ERR_INVALID_ARG),
                        ((-1, 5, 100, 10), S.OZEMU_ERR_INVALID_ARG)]:
