@@ -67,7 +67,8 @@ def parse():
     ap.add_argument("--blocked-mn", type=int, default=4096, help="blocked: m = n")
     ap.add_argument("--blocked-k", type=int, default=262144, help="blocked: inner dimension")
     ap.add_argument("--k-slab", type=int, default=0,
-                    help="blocked: slab length (0: the plan's accumulation cap)")
+                    help="blocked: slab length (0: the fewest equal slabs within the "
+                         "accumulation cap)")
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--width", type=int, default=4096)
     return ap.parse_args()
@@ -520,7 +521,12 @@ def blocked_main(args):
     A = torch.from_numpy(A_h).cuda()
     B = torch.from_numpy(B_h).cuda()
     plan = oz.Plan(num_moduli=args.moduli, scaling=args.scaling)
-    k_slab = args.k_slab or plan.k_max()
+    cap = plan.k_max()
+    if args.k_slab:
+        k_slab = args.k_slab
+    else:  # equal slabs, whole 64-term K steps, within the cap
+        count = -(-k // cap)
+        k_slab = min(cap, -(-(-(-k // count)) // 64) * 64)
     C = torch.empty((n, n), dtype=torch.float64, device="cuda")
     ws = torch.empty(oz.blocked_workspace_size(plan, n, n, k, k_slab), dtype=torch.uint8,
                      device="cuda")
