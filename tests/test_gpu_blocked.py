@@ -73,3 +73,26 @@ def test_blocked_single_slab_equals_unblocked_call():
     again = host(oz.dgemm_blocked(dA, dB, plan, k, workspace=ws))
     torch.cuda.synchronize()
     assert np.array_equal(one, full) and np.array_equal(eight, full) and np.array_equal(again, full)
+
+
+def test_blocked_with_leading_dimensions():
+    """Operands that are column slices of wider matrices (lda > k, ldb > n)
+    and C written into a wider buffer: each slab's columns of A and rows of
+    B are found through the leading dimensions."""
+    import torch
+    m, n, k = 130, 90, 700
+    A, B = operand_pair(m, n, k, 1.0, 8)
+    plan = oz.Plan(num_moduli=16, scaling="W")
+    wideA = torch.zeros((m, k + 37), dtype=torch.float64, device="cuda")
+    wideB = torch.zeros((k, n + 5), dtype=torch.float64, device="cuda")
+    wideA[:, 3:3 + k] = dev(A)
+    wideB[:, 1:1 + n] = dev(B)
+    wideC = torch.full((m, n + 11), 7.0, dtype=torch.float64, device="cuda")
+    dA, dB = wideA[:, 3:3 + k], wideB[:, 1:1 + n]
+    assert dA.stride(0) == k + 37 and dB.stride(0) == n + 5
+    oz.dgemm_blocked(dA, dB, plan, 256, out=wideC[:, 2:2 + n])
+    torch.cuda.synchronize()
+    Cw = host(wideC)
+    ref = scheme.emulate(A, B, plan.moduli(), "W", blas=True, keep=False)["C"]
+    assert np.array_equal(Cw[:, 2:2 + n], ref)
+    assert (Cw[:, :2] == 7.0).all() and (Cw[:, 2 + n:] == 7.0).all()
