@@ -438,7 +438,8 @@ __global__ void zero_c_kernel(int64_t m, int64_t n, double* C, int64_t ldc) {
 
 // Grouped Reconstruct; a problem with k = 0 gets zeros.
 template <int D>
-__global__ __launch_bounds__(kThreads) void group_reconstruct_kernel(GroupArgs g) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(D <= 8 ? 5 : 1)))
+void group_reconstruct_kernel(GroupArgs g) {
     const int32_t* pre = g.prefix + kGCrt * (g.count + 1);
     const int p = group_find(pre, g.count, blockIdx.x);
     const GProblem& P = g.probs[p];
