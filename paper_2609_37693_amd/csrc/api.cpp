@@ -128,6 +128,18 @@ ozemu_status check_plan(ozemu_plan plan) {
     return ok();
 }
 
+// The reconstruction caps of the whole inner dimension (modes F53 and W);
+// the accumulation cap is checked separately.
+ozemu_status check_window(const ozemu::Plan& p, int64_t k) {
+    if (p.scaling == OZEMU_SCALE_F53 && k > 0 && !ozemu::window_holds(p, k, 53, 53))
+        return fail(OZEMU_ERR_K_TOO_LARGE,
+                    "k = " + std::to_string(k) +
+                        " exceeds the reconstruction cap of this modulus set at 53 bits");
+    if (p.scaling == OZEMU_SCALE_WINDOW && k > 0 && ozemu::window_bits(p, k) < 2)
+        return fail(OZEMU_ERR_K_TOO_LARGE, "modulus product too small for this k");
+    return ok();
+}
+
 ozemu_status check_shape(const ozemu::Plan& p, int64_t m, int64_t n, int64_t k) {
     if (m < 0 || n < 0 || k < 0) return fail(OZEMU_ERR_INVALID_ARG, "negative dimension");
     if (m > (1ll << 31) || n > (1ll << 31)) return fail(OZEMU_ERR_INVALID_ARG, "dimension too large");
@@ -135,12 +147,7 @@ ozemu_status check_shape(const ozemu::Plan& p, int64_t m, int64_t n, int64_t k) 
         return fail(OZEMU_ERR_K_TOO_LARGE,
                     "k = " + std::to_string(k) + " exceeds the INT32 accumulation cap " +
                         std::to_string(p.kappa_acc) + " of this modulus set");
-    if (p.scaling == OZEMU_SCALE_F53 && k > 0 && !ozemu::window_holds(p, k, 53, 53))
-        return fail(OZEMU_ERR_K_TOO_LARGE,
-                    "k = " + std::to_string(k) +
-                        " exceeds the reconstruction cap of this modulus set at 53 bits");
-    if (p.scaling == OZEMU_SCALE_WINDOW && k > 0 && ozemu::window_bits(p, k) < 2)
-        return fail(OZEMU_ERR_K_TOO_LARGE, "modulus product too small for this k");
+    if (ozemu_status s = check_window(p, k)) return s;
     if (is_fp(p) && k > 0) {
         int ba = 53, bb = 53;
         if (p.scaling == OZEMU_SCALE_WINDOW) {
@@ -152,18 +159,6 @@ ozemu_status check_shape(const ozemu::Plan& p, int64_t m, int64_t n, int64_t k) 
     }
     if (p.scaling == OZEMU_SCALE_BOUND && k > 524287)
         return fail(OZEMU_ERR_K_TOO_LARGE, "bound product would overflow INT32");
-    return ok();
-}
-
-// The reconstruction caps of the whole inner dimension (INT8 plans, modes
-// F53 and W); the accumulation cap is checked separately.
-ozemu_status check_window(const ozemu::Plan& p, int64_t k) {
-    if (p.scaling == OZEMU_SCALE_F53 && k > 0 && !ozemu::window_holds(p, k, 53, 53))
-        return fail(OZEMU_ERR_K_TOO_LARGE,
-                    "k = " + std::to_string(k) +
-                        " exceeds the reconstruction cap of this modulus set at 53 bits");
-    if (p.scaling == OZEMU_SCALE_WINDOW && k > 0 && ozemu::window_bits(p, k) < 2)
-        return fail(OZEMU_ERR_K_TOO_LARGE, "modulus product too small for this k");
     return ok();
 }
 
