@@ -500,10 +500,18 @@ __global__ __launch_bounds__(kEncThreads) void encode_fp_a_kernel(
     // row argument of store_codes (bytes, or codes for FP6) and plane bytes
     const int64_t kb_pad = kBits == 4 ? k_pad / 2 : k_pad;
     const int64_t plane_stride = m_pad * (kBits == 6 ? k_pad / 4 * 3 : kb_pad);
+    // a workgroup covers a tile of 64 rows x 64 codes (FP4: 32 rows x 128
+    // codes), so each plane's stores fill one contiguous region of its block
+    // (4 KB of FP8, 3 KB of FP6, 2 KB of FP4), as in encode_a
+    constexpr int kTileCodes = kBits == 4 ? 128 : 64;
+    constexpr int kTpr = kTileCodes / kEncVec;  // threads per tile row
+    constexpr int kTileRows = kEncThreads / kTpr;
     const int64_t c = (int64_t)blockIdx.x * kChunksPerBlock + threadIdx.x;
-    const int64_t cpr = k_pad / kEncVec;
-    const int64_t i = c / cpr;
-    const int64_t h = (c % cpr) * kEncVec;
+    const int64_t tiles_k = k_pad / kTileCodes;
+    const int64_t tile = c >> 8;
+    const int t = (int)(c & 255);
+    const int64_t i = (tile / tiles_k) * kTileRows + t / kTpr;
+    const int64_t h = (tile % tiles_k) * kTileCodes + (t % kTpr) * kEncVec;
     if (i >= m_pad) return;
     uint8_t code[kEncVec];
     if (i >= m || h >= k) {  // padding: code 0 is +0 in both formats
